@@ -1,0 +1,369 @@
+"""Pins of the FP64 CPU reference against facts fixed by the paper and by
+mathematics (CPU only).  Each test is chosen so that a plausible mistake in
+the reference (dropped term, wrong sign, swapped l/m, wrong bin centre,
+missing conjugate half, missing w-shift) fails at least one of them."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import psf_synth as ps
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+C = 299792458.0
+
+
+# ---------------------------------------------------------------- helpers
+def ramp_observation(n_samples, bin_len, g_m_per_sample, nu=1.4e9, axis=0, n_ch=1,
+                     bin_ch=1, dnu=0.0, u0=(1234.5, -321.0, 45.0)):
+    """One baseline whose uvw run linearly in time (slope g along ``axis``),
+    channels spaced by dnu.  The bin centre is the exact centre of the ramp."""
+    j = np.arange(n_samples, dtype=np.float64)
+    uvw = np.tile(np.asarray(u0, np.float64), (n_samples, 1))
+    uvw[:, axis] += g_m_per_sample * j
+    n_tb = -(-n_samples // bin_len)
+    centre = np.tile(np.asarray(u0, np.float64), (n_tb, 1))
+    for T in range(n_tb):
+        jj = j[T * bin_len:min(n_samples, (T + 1) * bin_len)]
+        centre[T, axis] += g_m_per_sample * jj.mean()
+    freqs = nu + dnu * (np.arange(n_ch) - 0.5 * (n_ch - 1))
+    bl_bin = np.array([[bin_len, bin_ch]], np.int32)
+    koff, tboff = ps.bin_tables(n_samples, n_ch, bl_bin)
+    return ps.Observation(ant_enu=np.zeros((2, 3)), bl_ant=np.array([[0, 1]], np.int32),
+                          times_s=j, uvw_m=uvw[None], freq_hz=freqs, bl_bin=bl_bin,
+                          bl_koff=koff, bl_tboff=tboff, uvw_c_m=centre,
+                          W=np.ones(int(koff[-1]), np.float32))
+
+
+def dirichlet(n, d):
+    if abs(math.sin(math.pi * d)) < 1e-300:
+        return 1.0
+    return math.sin(n * math.pi * d) / (n * math.sin(math.pi * d))
+
+
+def load_dirichlet_pins():
+    rows = []
+    with open(os.path.join(HERE, "golden", "dirichlet_pins.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                n, d, D = line.split()
+                rows.append((int(n), float(d), float(D)))
+    return rows
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    obs = ps.observation(1)
+    src = ps.sources(1)[0]
+    return obs, src
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return ps.tiny_random(3, n_ant=4, n_t=7, n_ch=3, nt=3, nc=2)
+
+
+# ---------------------------------------------------------------- D_k
+def test_D_is_one_at_phase_centre(cfg1):
+    # Section 4: at l0 = 0 the averaged visibilities carry no decorrelation.
+    obs, _ = cfg1
+    D = orc.decorr(obs, 0.0, 0.0)
+    assert np.array_equal(D, np.ones_like(D))
+
+
+def test_D_is_one_for_single_sample_bins():
+    obs = ps.tiny_random(5, n_t=5, n_ch=3, nt=1, nc=1)
+    D = orc.decorr(obs, 0.02, -0.03)
+    assert np.array_equal(D, np.ones_like(D))
+
+
+@pytest.mark.parametrize("n,d,expect", load_dirichlet_pins())
+def test_linear_ramp_matches_dirichlet_golden(n, d, expect):
+    # A time ramp: per-sample phase step d turns = g nu l0 / c.
+    nu, l0 = 1.4e9, 0.01
+    g = d * C / (nu * l0)
+    obs = ramp_observation(3 * n, n, g, nu=nu, axis=0)
+    D = orc.decorr(obs, l0, 0.0)
+    assert np.allclose(D.real, expect, atol=1e-12, rtol=0)
+    assert np.max(np.abs(D.imag)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 8, 17])
+def test_frequency_ramp_matches_dirichlet(n):
+    # Channels spaced dnu at fixed uvw: phase step u dnu m0 / c per channel.
+    nu, m0, dnu = 1.4e9, -0.02, 5e6
+    obs = ramp_observation(2, 1, 0.0, nu=nu, n_ch=2 * n, bin_ch=n, dnu=dnu, u0=(300.0, 2100.0, 0.0))
+    D = orc.decorr(obs, 0.0, m0)
+    d = 2100.0 * dnu * m0 / C
+    assert np.allclose(D, dirichlet(n, d), atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("x", [0.4, 1.3, 2.9])
+def test_discrete_mean_tends_to_paper_sinc(x):
+    # Section 3.1: boxcar average -> sinc(dPsi/2).  The discrete mean over n
+    # samples is x/(n sin(x/n)) * sinc(x), x = dPsi/2, i.e. relative gap
+    # x^2/(6 n^2) + O(n^-4).
+    nu, l0 = 1.4e9, 0.01
+    for n in (16, 64, 256):
+        d = x / (n * math.pi)
+        g = d * C / (nu * l0)
+        D = orc.decorr(ramp_observation(n, n, g, nu=nu), l0, 0.0)[0].real
+        sinc = math.sin(x) / x
+        rel = D / sinc - 1.0
+        assert abs(rel - x * x / (6 * n * n)) < 0.02 * x ** 4 / n ** 4 + 1e-12
+
+
+def test_earth_rotation_D_close_to_paper_sinc():
+    # On true Earth-rotation tracks D is not exactly a ramp; the paper's
+    # Method-1 closed form sinc(dPsi/2) sinc(dPhi/2) with dPsi over the bin's
+    # time span must still agree to ~1e-5 for 20-30 s bins at 1 km.
+    obs = ps.observation(1)
+    l0, m0 = 0.5 * ps.DEG, 0.3 * ps.DEG
+    D = orc.decorr(obs, l0, m0)
+    tab = orc.bin_table(obs)
+    _, bl_enu = ps.baselines(obs.ant_enu)
+    dt = obs.times_s[1] - obs.times_s[0]
+    nu = obs.freq_hz[0]
+    n0 = math.sqrt(1 - l0 * l0 - m0 * m0)
+    ts = obs.times_s[tab.t0] - 0.5 * dt
+    te = obs.times_s[tab.t1 - 1] + 0.5 * dt
+    us = np.stack([ps.uvw_tracks(bl_enu[b:b + 1], np.array([ps.OMEGA_EARTH * t]))[0, 0] for b, t in zip(tab.b, ts)])
+    ue = np.stack([ps.uvw_tracks(bl_enu[b:b + 1], np.array([ps.OMEGA_EARTH * t]))[0, 0] for b, t in zip(tab.b, te)])
+    dpsi = 2 * math.pi * ((us - ue) @ np.array([l0, m0, n0 - 1])) * nu / C
+    x = dpsi / 2
+    sinc = np.sinc(x / math.pi)                  # np.sinc(y) = sin(pi y)/(pi y)
+    n = (tab.t1 - tab.t0).astype(np.float64)
+    dirich = np.sin(x) / (n * np.sin(x / n))     # discrete mean of the same ramp
+    # the discrete mean sits x^2/(6 n^2) above the paper's continuous sinc ...
+    assert np.max(np.abs(D.real - sinc)) < 2e-5
+    assert np.allclose(D.real / sinc - 1, x * x / (6 * n * n), rtol=0.05, atol=1e-9)
+    # ... and equals the Dirichlet form up to the tracks' small curvature
+    assert np.max(np.abs(D.real - dirich)) < 1e-8
+    assert np.max(np.abs(D.imag)) < 1e-4
+
+
+def test_decorr_matches_explicit_loops(tiny):
+    D = orc.decorr(tiny, 0.031, -0.017)
+    Db = orc.decorr_brute(tiny, 0.031, -0.017)
+    assert np.max(np.abs(D - Db)) < 1e-12      # FP64 rounding of u ~ 1e4 wavelengths
+
+
+def test_decorr_sign_convention(tiny):
+    D = orc.decorr(tiny, 0.031, -0.017)
+    Dp = orc.decorr(tiny, 0.031, -0.017, sign=+1.0)
+    assert np.max(np.abs(Dp - np.conj(D))) < 1e-15
+    assert np.max(np.abs(D.imag)) > 1e-6     # the sign is observable
+
+
+def test_decorr_gradient_matches_fd(tiny):
+    l0, m0, h = 0.021, -0.013, 1e-7
+    D, dl, dm = orc.decorr_with_grad(tiny, l0, m0)
+    fl = (orc.decorr(tiny, l0 + h, m0) - orc.decorr(tiny, l0 - h, m0)) / (2 * h)
+    fm = (orc.decorr(tiny, l0, m0 + h) - orc.decorr(tiny, l0, m0 - h)) / (2 * h)
+    scale = max(np.max(np.abs(dl)), np.max(np.abs(dm)))
+    assert np.max(np.abs(dl - fl)) < 1e-6 * scale
+    assert np.max(np.abs(dm - fm)) < 1e-6 * scale
+
+
+# ---------------------------------------------------------------- P
+def effective_psf_closed_form(obs, src):
+    # Section 2.2: the effective PSF is the inverse transform of the weighted
+    # sampling function: both conjugate halves of a unit-weight delta give
+    # 2 cos(2 pi (u l + v m)) at the bin centres, no decorrelation, no w.
+    out = np.zeros((src.nl, src.nm))
+    for k in range(obs.K):
+        b, = np.nonzero(obs.bl_koff[1:] > k)[0][:1]
+        nt, nc = obs.bl_bin[b]
+        n_fb = -(-obs.n_ch // nc)
+        T, F = divmod(k - obs.bl_koff[b], n_fb)
+        ch = obs.freq_hz[F * nc:min(obs.n_ch, (F + 1) * nc)]
+        u, v, _ = obs.uvw_c_m[obs.bl_tboff[b] + T] * ch.mean() / C
+        for i in range(src.nl):
+            li = src.l_first + i * src.dl
+            mj = src.m_first + np.arange(src.nm) * src.dm
+            out[i] += 2 * obs.W[k] * np.cos(2 * math.pi * (u * li + v * mj))
+    return out
+
+
+def test_phase_centre_patch_is_effective_psf(cfg1):
+    obs, _ = cfg1
+    src = ps.Source.centred(0.0, 0.0, 17, 20 * ps.ARCSEC)
+    P = orc.patch_factored(obs, src)
+    E = effective_psf_closed_form(obs, src)
+    assert orc.peak_normalised_error(P, E)[0] < 1e-12
+
+
+def test_peak_equals_sum_of_weighted_D(cfg1):
+    obs, src = cfg1
+    D = orc.decorr(obs, src.l0, src.m0)
+    P = orc.patch_factored(obs, src, D)
+    c = src.nl // 2
+    peak = 2.0 * sum(float(obs.W[k]) * D[k].real for k in range(obs.K))
+    assert abs(P[c, c] - peak) < 1e-12 * abs(peak)
+    assert P[c, c] == pytest.approx(P.max(), rel=1e-12)
+
+
+def test_brute_force_with_explicit_conjugates(cfg1):
+    obs, src = cfg1
+    small = ps.Source.centred(src.l0, src.m0, 9, 7 * ps.ARCSEC, nm=11)
+    Pb = orc.patch_brute(obs, small)
+    P = orc.patch_factored(obs, small)
+    assert np.max(np.abs(Pb.imag)) < 1e-13 * np.max(np.abs(Pb.real))
+    assert orc.peak_normalised_error(Pb.real, P)[0] < 1e-12
+
+
+def test_single_bin_closed_form():
+    obs = ramp_observation(4, 4, 3.0, u0=(900.0, -2500.0, 310.0))
+    l0, m0 = 0.013, 0.021
+    src = ps.Source.centred(l0, m0, 5, 30 * ps.ARCSEC, nm=3)
+    D = orc.decorr(obs, l0, m0)[0]
+    n0 = math.sqrt(1 - l0 * l0 - m0 * m0)
+    u, v, w = obs.uvw_c_m[0] * obs.freq_hz[0] / C
+    P = orc.patch_factored(obs, src)
+    for i in range(src.nl):
+        for j in range(src.nm):
+            x = i * src.dl + src.l_first - l0
+            y = j * src.dm + src.m_first - m0
+            th = 2 * math.pi * ((u - w * l0 / n0) * x + (v - w * m0 / n0) * y)
+            want = 2 * (D.real * math.cos(th) - D.imag * math.sin(th))
+            assert P[i, j] == pytest.approx(want, abs=1e-12)
+
+
+def test_l_axis_is_first_index():
+    # Only u varies and the w-shift vanishes (w = 0): P must vary along i (l)
+    # and be constant along j (m) -- a swapped l/m grid fails this.
+    obs = ramp_observation(6, 3, 2.0, u0=(1500.0, 0.0, 0.0))
+    src = ps.Source.centred(0.004, 0.006, 7, 40 * ps.ARCSEC, nm=5)
+    P = orc.patch_factored(obs, src)
+    assert np.max(np.abs(P - P[:, :1])) < 1e-12 * np.max(np.abs(P))
+    assert np.max(np.abs(P - P[:1, :])) > 1e-3 * np.max(np.abs(P))
+
+
+def test_mirror_identity_of_sign_convention(tiny):
+    # The literal "+" sign in both D and the imaging exponent gives the
+    # point-mirrored patch of the paper's convention.
+    src = ps.Source.centred(0.03, -0.02, 9, 25 * ps.ARCSEC)
+    P = orc.patch_factored(tiny, src)
+    Dp = orc.decorr(tiny, src.l0, src.m0, sign=+1.0)
+    Pp = orc.patch_factored(tiny, src, D=Dp, sign=+1.0)
+    # literal form == paper's patch at -x, -y (centred grid => index reversal)
+    Pm = orc.patch_factored(tiny, src, D=np.conj(Dp), sign=-1.0)
+    assert orc.peak_normalised_error(Pp, Pm)[0] < 1e-12
+    assert orc.peak_normalised_error(Pm, P[::-1, ::-1])[0] < 1e-12
+    assert orc.peak_normalised_error(P, P[::-1, ::-1])[0] > 1e-6
+
+
+def test_linear_in_weights(tiny):
+    src = ps.Source.centred(0.01, 0.02, 7, 20 * ps.ARCSEC)
+    P1 = orc.patch_factored(tiny, src)
+    t2 = ps.Observation(**{**tiny.__dict__, "W": (4.0 * tiny.W).astype(np.float32)})   # exact in float32
+    P2 = orc.patch_factored(t2, src)
+    assert orc.peak_normalised_error(P2, 4.0 * P1)[0] < 1e-14
+    z = ps.Observation(**{**tiny.__dict__, "W": np.zeros_like(tiny.W)})
+    assert np.all(orc.patch_factored(z, src) == 0.0)
+
+
+def test_wshift_is_first_order_correct():
+    # The linearised w-shift agrees with the exact w phase to second order in
+    # the pixel offset.
+    obs = ps.tiny_random(7, n_ant=5, n_t=4, n_ch=2, nt=2, nc=2, radius_m=20000.0)
+    l0, m0 = 0.05, -0.04
+    errs, errs_noshift = [], []
+    for cell in (1e-7, 5e-8, 2.5e-8):           # patch well inside one fringe
+        src = ps.Source.centred(l0, m0, 5, cell)
+        D = orc.decorr(obs, l0, m0)
+        Pw = orc.patch_fullw(obs, src, D)
+        P = orc.patch_factored(obs, src, D)
+        errs.append(np.max(np.abs(P - Pw)))
+        # no shift: u' = u is the linearisation about the phase centre instead
+        uk = orc.bin_centres_lambda(obs)
+        x, y = orc.pixel_offsets(src)
+        c = obs.W * D
+        P0 = 2 * np.real(np.einsum("k,ki,kj->ij", c, np.exp(2j * np.pi * uk[:, 0, None] * x),
+                                   np.exp(2j * np.pi * uk[:, 1, None] * y)))
+        errs_noshift.append(np.max(np.abs(P0 - Pw)))
+    # second order or better in the offset (the real part of the lowest term
+    # can cancel between conjugate halves), and far below the error left when
+    # the shift is dropped
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+    assert all(e < 0.05 * e0 for e, e0 in zip(errs, errs_noshift))
+
+
+def test_patch_pixels_agree_with_full_patch(cfg1):
+    obs, src = cfg1
+    P = orc.patch_factored(obs, src)
+    ii, jj = [0, 32, 64, 10], [0, 32, 17, 64]
+    vals = orc.patch_pixels(obs, src, ii, jj)
+    assert np.max(np.abs(vals - P[ii, jj])) < 1e-12 * np.max(np.abs(P))
+
+
+def test_ragged_and_bda_bins_brute_vs_factored():
+    obs = ps.tiny_random(11, n_ant=5, n_t=11, n_ch=5, nt=4, nc=3, bda=True)
+    assert len(set(map(tuple, obs.bl_bin))) > 1
+    src = ps.Source.centred(0.02, 0.01, 5, 15 * ps.ARCSEC, nm=4)
+    Pb = orc.patch_brute(obs, src)
+    P = orc.patch_factored(obs, src)
+    assert np.max(np.abs(Pb.imag)) < 1e-12 * np.max(np.abs(P))
+    assert orc.peak_normalised_error(Pb.real, P)[0] < 1e-12
+
+
+# ---------------------------------------------------------------- gradient
+def _grad_setup(n_src=3, seed=0):
+    obs = ps.tiny_random(21, n_ant=5, n_t=9, n_ch=4, nt=3, nc=2, radius_m=5000.0)
+    g = np.random.default_rng(seed)
+    srcs, fl, tg = [], [], []
+    for _ in range(n_src):
+        l0, m0 = g.uniform(-0.03, 0.03, 2)
+        s = ps.Source.centred(l0, m0, 9, 10 * ps.ARCSEC, nm=7)
+        f = 10 ** g.uniform(-1, 0)
+        moved = s.with_direction(l0 + g.normal(0, 2 * ps.ARCSEC), m0 + g.normal(0, 2 * ps.ARCSEC))
+        srcs.append(s)
+        fl.append(f)
+        tg.append(f * orc.patch_factored(obs, moved))
+    return obs, srcs, np.array(fl), tg
+
+
+def test_gradient_matches_central_differences():
+    obs, srcs, fl, tg = _grad_setup()
+    L, g_lm, g_f = orc.loss_grad_analytic(obs, srcs, fl, tg)
+    fd = orc.loss_grad_fd(obs, srcs, fl, tg)
+    assert L == pytest.approx(orc.loss_value(obs, srcs, fl, tg), rel=1e-12)
+    assert np.max(np.abs(g_lm - fd)) < 1e-6 * np.max(np.abs(fd))
+    # flux gradient: d/df sum (fP - T)^2 = 2 sum (fP - T) P, checked by FD in f
+    h = 1e-6
+    for n in range(len(srcs)):
+        fp, fm = fl.copy(), fl.copy()
+        fp[n] += h
+        fm[n] -= h
+        fdf = (orc.loss_value(obs, srcs, fp, tg) - orc.loss_value(obs, srcs, fm, tg)) / (2 * h)
+        assert g_f[n] == pytest.approx(fdf, rel=1e-6)
+
+
+def test_gradient_zero_at_generating_parameters():
+    obs, srcs, fl, _ = _grad_setup(seed=1)
+    tg = [f * orc.patch_factored(obs, s) for s, f in zip(srcs, fl)]
+    L, g_lm, g_f = orc.loss_grad_analytic(obs, srcs, fl, tg)
+    assert L < 1e-20
+    assert np.max(np.abs(g_lm)) < 1e-6 and np.max(np.abs(g_f)) < 1e-9
+
+
+# ---------------------------------------------------------------- properties
+def test_random_tiny_observations_brute_vs_factored():
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=12, deadline=None, derandomize=True)
+    @hyp.given(seed=st.integers(0, 10_000), nt=st.integers(1, 4), nc=st.integers(1, 3),
+               l0=st.floats(-0.05, 0.05), m0=st.floats(-0.05, 0.05))
+    def check(seed, nt, nc, l0, m0):
+        obs = ps.tiny_random(seed, n_ant=3, n_t=5, n_ch=3, nt=nt, nc=nc)
+        src = ps.Source.centred(l0, m0, 3, 30 * ps.ARCSEC, nm=4)
+        Pb = orc.patch_brute(obs, src)
+        P = orc.patch_factored(obs, src)
+        assert np.max(np.abs(Pb.imag)) < 1e-12 * max(1.0, np.max(np.abs(P)))
+        assert np.max(np.abs(Pb.real - P)) < 1e-12 * max(1.0, np.max(np.abs(P)))
+
+    check()
