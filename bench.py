@@ -1,0 +1,157 @@
+"""Throughput of the distorted-PSF hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec split_bf16]
+
+One step = one PSF of the MeerKAT-shaped workload (64 antennas, 2016
+baselines, 3600 x 2 s, 32 channels over 1.3-1.5 GHz, 20 s x 4 channel bins:
+K = 5,806,080 averaged visibilities; one source at 1 deg; 257 x 257 patch at
+1.5"): decorrelation factors, phase factors, contraction and finalise, all
+inside one psf_patch call on device-resident inputs.  The value is
+vis.pixel terms/s (K x 257^2 one-sided terms per PSF).
+
+Printed: one JSON line with the headline (split-BF16 unless --prec says
+otherwise), the same workload in plain FP32 for comparison, the roofline of
+the contraction kernel measured with HIP events on its launch stream, and
+the FP64 CPU reference timed on a bounded sample on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "plain_bf16": 2516.6, "fp32": 157.3}
+# executed matrix-core flops per useful one-sided term: 2 real MACs (Re*Re and
+# Im*Im) per term, times 3 products for the split forms
+FLOPS_PER_TERM = {"split_bf16": 12.0, "split_fp16": 12.0, "plain_bf16": 4.0, "fp32": 4.0}
+DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "plain_bf16": "bf16", "fp32": "f32"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="split_bf16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baselines", type=int, default=128,
+                    help="baselines in the CPU-reference sample")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="if > 0: only run this many steps of --prec (for rocprofv3) and print nothing else")
+    return ap.parse_args()
+
+
+def time_prec(pk, torch, dobs, src, prec, steps, warmup, ws):
+    for _ in range(warmup):
+        pk.patch(dobs, src, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    out = torch.empty((src.nl, src.nm), dtype=torch.float32, device="cuda")
+    pk.psf_timing_read()
+    pk.psf_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk.patch(dobs, src, prec=prec, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nk = pk.psf_timing_read()
+    pk.psf_timing_enable(False)
+    return wall / steps * 1e3, kms / max(nk, 1), out
+
+
+def cpu_baseline(obs, src, n_bl_sub):
+    """The FP64 oracle (decorr + factored patch) on the first n_bl_sub baselines."""
+    import numpy as np
+
+    import oracle as orc
+    import psf_synth as ps
+    B = min(n_bl_sub, obs.n_bl)
+    k1, tb1 = int(obs.bl_koff[B]), int(obs.bl_tboff[B])
+    sub = ps.Observation(ant_enu=obs.ant_enu, bl_ant=obs.bl_ant[:B], times_s=obs.times_s,
+                         uvw_m=obs.uvw_m[:B], freq_hz=obs.freq_hz, bl_bin=obs.bl_bin[:B],
+                         bl_koff=obs.bl_koff[:B + 1], bl_tboff=obs.bl_tboff[:B + 1],
+                         uvw_c_m=obs.uvw_c_m[:tb1], W=obs.W[:k1], name="sample")
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = None
+    t0 = time.perf_counter()
+    D = orc.decorr(sub, src.l0, src.m0)
+    P = orc.patch_factored(sub, src, D)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(P).all()
+    terms = k1 * src.nl * src.nm
+    return {"value": terms / dt, "unit": "terms/s", "cores": blas_threads or len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"FP64 oracle decorr + factored patch over the first {B} of {obs.n_bl} baselines "
+                      f"({k1} of {obs.K} bins) x {src.nl}x{src.nm} pixels, {dt:.1f} s; host has "
+                      f"{len(os.sched_getaffinity(0))} usable cores"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); multi-GPU sharding is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2009_07010_amd as pk
+    import psf_synth as ps
+    assert torch.cuda.is_available(), "needs a GPU"
+    obs = ps.observation(2, seed=a.seed)
+    src = ps.sources(2, seed=a.seed)[0]
+    dobs = pk.DeviceObservation(obs)
+    ws = pk.Workspace()
+    terms = obs.K * src.nl * src.nm
+
+    if a.profile_steps > 0:
+        for _ in range(a.profile_steps):
+            pk.patch(dobs, src, prec=a.prec, workspace=ws)
+        torch.cuda.synchronize()
+        print(f"profiled {a.profile_steps} steps of {a.prec}", flush=True)
+        return
+
+    ms, kms, _ = time_prec(pk, torch, dobs, src, a.prec, a.steps, a.warmup, ws)
+    ms32, kms32, _ = time_prec(pk, torch, dobs, src, "fp32", max(3, a.steps // 4), 1, ws)
+    flops = FLOPS_PER_TERM[a.prec] * terms
+    achieved = flops / (kms * 1e-3) / 1e12
+    line = {
+        "metric": "PSF vis.pixel terms/s at <=1e-5 rel err vs FP64 (split-BF16 vs FP32)",
+        "value": terms / (ms * 1e-3),
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[a.prec],
+        "data": "synthetic",
+        "config": {"workload": "MeerKAT-shaped: 64 antennas (2016 baselines), 3600 x 2 s, 32 ch over "
+                               "1.3-1.5 GHz, 20 s x 4 ch bins (K=5,806,080), 1 source at 1 deg, 257x257 "
+                               "patch at 1.5 arcsec",
+                   "K": obs.K, "patch": [src.nl, src.nm], "precision": a.prec, "seed": a.seed},
+        "psfs_per_s": 1e3 / ms,
+        "fp32": {"ms_per_step": ms32, "terms_per_s": terms / (ms32 * 1e-3),
+                 "contraction_ms": kms32,
+                 "contraction_tflops": 4.0 * terms / (kms32 * 1e-3) / 1e12},
+        "roofline": {"bound": "mfma", "kernel": f"k_patch<{a.prec}>", "achieved": achieved,
+                     "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[a.prec],
+                     "traffic": None, "kernel_ms": kms,
+                     "per_unit": f"{FLOPS_PER_TERM[a.prec]:g} matrix-core flops per useful term, "
+                                 f"{terms} terms per launch"},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

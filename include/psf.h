@@ -1,0 +1,164 @@
+/*
+ * psf.h -- C ABI of libpsfdecorr: position-dependent (smearing-distorted)
+ * point spread functions of averaged visibilities on AMD MI355X (gfx950).
+ *
+ * Problem (Atemkeng et al. 2020, "Fast algorithms to approximate the
+ * position-dependent point spread function responses in radio
+ * interferometric wide-field imaging"):
+ *
+ *   Averaging visibilities over a time x frequency bin [section 2.3, the
+ *   averaging integral over the sampling bin] multiplies the bin-centre
+ *   visibility of a point source at (l0, m0) by a distortion factor
+ *   [section 3.1, sampled distortion = bin-centre phase x distortion].
+ *   Read discretely, for bin k with samples s at uvw u_s and centre u_k
+ *   (wavelengths), n0 = sqrt(1 - l0^2 - m0^2):
+ *
+ *     phi_s = (u_s - u_k) l0 + (v_s - v_k) m0 + (w_s - w_k)(n0 - 1)
+ *     D_k   = mean_s exp(-2 pi i phi_s)
+ *
+ *   The distorted PSF [section 2.3, distorted-PSF equation] about the
+ *   source [section 2.2, offset indexing], both conjugate halves summed and
+ *   the w-term linearised into u' = u - w l0/n0, v' = v - w m0/n0:
+ *
+ *     P_ij = 2 Re sum_k W_k D_k exp(2 pi i (u'_k x_i + v'_k y_j)),
+ *     x_i = l_first + i dl - l0,   y_j = m_first + j dm - m0.
+ *
+ * Conventions for every entry point:
+ *  - Every array pointer is a DEVICE pointer owned by the caller, except
+ *    those documented as host pointers (h_*).  The library allocates no
+ *    device memory and keeps no device state; scratch memory is the
+ *    caller's workspace, sized with psf_workspace_bytes().
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the null stream), performs no host<->device synchronisation and
+ *    no allocation, and clears what it needs with kernels (no memset
+ *    nodes), so it may be captured into a HIP graph.  psf_autotune and
+ *    psf_timing_* are the exceptions and say so.
+ *  - Scalar and shape checks run on the host before anything is launched.
+ *    A failed check returns PSF_EINVAL (or PSF_EWORKSPACE) and launches
+ *    nothing; psf_last_error() then holds a message (thread-local).
+ *    Launch failures return PSF_EDEVICE.  A device other than gfx950
+ *    returns PSF_EUNSUPPORTED.  No C++ exception crosses this boundary.
+ *  - Results are deterministic: partial sums are reduced in a fixed order
+ *    (no floating-point atomics), so repeated calls are bitwise identical.
+ */
+#ifndef PSFDECORR_PSF_H
+#define PSFDECORR_PSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSF_OK = 0,
+  PSF_EINVAL = -1,       /* bad argument, shape or pointer */
+  PSF_EWORKSPACE = -2,   /* workspace missing or too small */
+  PSF_EDEVICE = -3,      /* a HIP call or launch failed */
+  PSF_EUNSUPPORTED = -4  /* current device is not gfx950 / feature absent */
+} psf_status;
+
+/* Arithmetic of the patch contraction.  Phase arguments are always formed
+ * and reduced to turns in FP64; sin/cos, D_k and accumulation are FP32. */
+typedef enum {
+  PSF_FP32 = 0,        /* FP32 matrix-core products, FP32 accumulation */
+  PSF_SPLIT_BF16 = 1,  /* operands split hi+lo in BF16, 3 products, FP32 acc */
+  PSF_SPLIT_FP16 = 2,  /* operands split hi+lo in FP16, 3 products, FP32 acc */
+  PSF_PLAIN_BF16 = 3   /* single BF16 product: a negative control, not accurate */
+} psf_prec;
+
+/* One observation: high-resolution uvw tracks, channels and the bin table
+ * (all device arrays).  Bins are ordered (baseline, time bin, frequency bin):
+ * baseline b averages nt_b consecutive samples in time and nc_b consecutive
+ * channels; bins tile from the first sample, the last bin along each axis
+ * may be short.  Bin k = bl_koff[b] + T * ceil(n_ch / nc_b) + F. */
+typedef struct psf_obs {
+  int32_t n_bl;             /* baselines */
+  int32_t n_t;              /* high-resolution time samples per baseline */
+  int32_t n_ch;             /* channels */
+  int32_t reserved;         /* must be 0 */
+  int64_t K;                /* number of bins (averaged visibilities), one-sided */
+  int64_t n_tb;             /* number of time bins over all baselines */
+  const double* uvw_m;      /* [n_bl][n_t][3] uvw in metres */
+  const double* freq_hz;    /* [n_ch] channel centre frequencies (Hz) */
+  const int32_t* bl_bin;    /* [n_bl][2] {nt_b, nc_b}, both >= 1 */
+  const int64_t* bl_koff;   /* [n_bl + 1] first bin of each baseline, bl_koff[n_bl] = K */
+  const int64_t* bl_tboff;  /* [n_bl + 1] first time-bin row of each baseline, last = n_tb */
+  const double* uvw_c_m;    /* [n_tb][3] uvw (metres) at each time-bin centre; the
+                               centre frequency of a bin is the mean of its channels */
+  const float* W;           /* [K] weight of each averaged visibility */
+} psf_obs;
+
+/* One source and the absolute pixel grid of its patch: pixel (i, j) is at
+ * (l_first + i dl, m_first + j dm); the patch is row-major [nl][nm]
+ * (i along l, j along m).  out_off is the element offset of this patch in a
+ * concatenated output (P_all / G_all); psf_patch ignores it. */
+typedef struct psf_src {
+  double l0, m0;
+  double l_first, m_first;
+  double dl, dm;
+  int32_t nl, nm;           /* 1 .. 4096 each */
+  int64_t out_off;
+} psf_src;
+
+/* Workspace bytes needed by psf_patch (n_src = 1), psf_patch_batched and
+ * psf_patch_backward for these sources and precision.  h_srcs is a host
+ * array.  Writes the size to *out (host). */
+int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
+                        int prec, size_t* out);
+
+/* D_k for every bin [section 2.3 averaging; section 3.1 bin-centre
+ * factorisation], written as D[k][0] = Re, D[k][1] = Im (float, [K][2]).
+ * Phases relative to the bin centre are formed in FP64 and reduced to
+ * turns before FP32 sin/cos.  Needs no workspace. */
+int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream);
+
+/* The distorted PSF patch of one source [section 2.3, distorted-PSF
+ * equation], P [nl][nm] float.  D is [K][2] from psf_decorr, or NULL to
+ * compute it inside the call.  h_src is a host pointer. */
+int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec,
+              float* P, void* ws, size_t ws_bytes, void* stream);
+
+/* Many sources in one persistent launch: D_k and the phases are computed
+ * on the fly per work item (source, k-range), so nothing of size K is kept
+ * per source.  h_srcs (host) fixes sizes and offsets; d_srcs (device, same
+ * n_src entries with the same nl, nm, out_off) supplies directions and
+ * grids at run time, so a captured graph can be replayed with new
+ * directions.  tuning_json (host, may be NULL) is a table from
+ * psf_autotune.  P_all receives every patch at its out_off. */
+int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
+                      const psf_src* d_srcs, int prec, const char* tuning_json,
+                      float* P_all, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the patch with respect to the source direction, grid fixed:
+ * given G_all = dLoss/dP (same layout as P_all), writes
+ * grad_lm[s][0] = dLoss/dl0, grad_lm[s][1] = dLoss/dm0 (double, [n_src][2])
+ * through D_k, the w-shift and the pixel offsets.  prec selects the
+ * contraction arithmetic (PSF_FP32 or a split form). */
+int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
+                       const psf_src* d_srcs, const float* G_all, int prec,
+                       double* grad_lm, void* ws, size_t ws_bytes, void* stream);
+
+/* Times candidate launch shapes for these sources with HIP events and
+ * writes a JSON tuning table (host buffer json_out, capacity json_cap).
+ * Synchronises the stream: not capturable. */
+int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int prec,
+                 void* ws, size_t ws_bytes, char* json_out, size_t json_cap, void* stream);
+
+/* Optional timing of the contraction kernels: while enabled, every launch
+ * of a patch or adjoint contraction is bracketed by HIP events on its
+ * stream.  psf_timing_read synchronises and returns the summed kernel time
+ * (ms) and the number of launches since the last read.  Not capturable. */
+int psf_timing_enable(int on);
+int psf_timing_read(double* ms_total, int64_t* launches);
+
+const char* psf_strerror(int status);
+const char* psf_last_error(void);
+/* Library version string. */
+const char* psf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSFDECORR_PSF_H */

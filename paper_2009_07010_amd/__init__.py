@@ -1,0 +1,242 @@
+"""Position-dependent PSFs of averaged visibilities on AMD MI355X.
+
+Thin Python binding over the C ABI of ``libpsfdecorr.so`` (see
+``include/psf.h``): argument marshalling only.  Every step of the PSF
+computation runs in the library's HIP kernels; PyTorch supplies device
+memory and the stream.  There is no CPU fallback: if the library is not
+built, importing a function that needs it raises.
+
+Low-level names mirror the C ABI (``psf_decorr``, ``psf_patch``,
+``psf_patch_batched``, ``psf_patch_backward``, ``psf_workspace_bytes``,
+``psf_autotune``); ``DeviceObservation`` and the lower-case helpers below
+wrap them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsfdecorr.so")
+
+PSF_FP32, PSF_SPLIT_BF16, PSF_SPLIT_FP16, PSF_PLAIN_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp32": PSF_FP32, "split_bf16": PSF_SPLIT_BF16, "split_fp16": PSF_SPLIT_FP16,
+              "plain_bf16": PSF_PLAIN_BF16}
+PSF_OK, PSF_EINVAL, PSF_EWORKSPACE, PSF_EDEVICE, PSF_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+
+class PsfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class PsfObs(ctypes.Structure):
+    _fields_ = [("n_bl", ctypes.c_int32), ("n_t", ctypes.c_int32), ("n_ch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("K", ctypes.c_int64), ("n_tb", ctypes.c_int64),
+                ("uvw_m", ctypes.c_void_p), ("freq_hz", ctypes.c_void_p), ("bl_bin", ctypes.c_void_p),
+                ("bl_koff", ctypes.c_void_p), ("bl_tboff", ctypes.c_void_p), ("uvw_c_m", ctypes.c_void_p),
+                ("W", ctypes.c_void_p)]
+
+
+class PsfSrc(ctypes.Structure):
+    _fields_ = [("l0", ctypes.c_double), ("m0", ctypes.c_double), ("l_first", ctypes.c_double),
+                ("m_first", ctypes.c_double), ("dl", ctypes.c_double), ("dm", ctypes.c_double),
+                ("nl", ctypes.c_int32), ("nm", ctypes.c_int32), ("out_off", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "psf_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc),
+                                           ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "psf_decorr": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
+    "psf_patch": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P, _P,
+                                 ctypes.c_size_t, _P]),
+    "psf_patch_batched": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
+                                         ctypes.c_int, ctypes.c_char_p, _P, _P, ctypes.c_size_t, _P]),
+    "psf_patch_backward": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
+                                          _P, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
+    "psf_autotune": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc),
+                                    ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t, _P]),
+    "psf_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "psf_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "psf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "psf_last_error": (ctypes.c_char_p, []),
+    "psf_version": (ctypes.c_char_p, []),
+}
+EXPORTED = tuple(_SIGNATURES)
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -m paper_2009_07010_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != PSF_OK:
+        L = lib()
+        raise PsfError(status, f"{L.psf_strerror(status).decode()}: {L.psf_last_error().decode()}")
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def make_src(src, out_off: int = 0) -> PsfSrc:
+    """PsfSrc from any object with l0, m0, l_first, m_first, dl, dm, nl, nm."""
+    return PsfSrc(float(src.l0), float(src.m0), float(src.l_first), float(src.m_first), float(src.dl),
+                  float(src.dm), int(src.nl), int(src.nm), int(out_off))
+
+
+def src_array(srcs: Sequence) -> "ctypes.Array":
+    arr = (PsfSrc * len(srcs))()
+    off = 0
+    for n, s in enumerate(srcs):
+        arr[n] = make_src(s, off)
+        off += int(s.nl) * int(s.nm)
+    return arr
+
+
+# ---------------------------------------------------------------- raw ABI
+def psf_workspace_bytes(obs: PsfObs, h_srcs, prec) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().psf_workspace_bytes(ctypes.byref(obs), len(h_srcs), h_srcs, _prec(prec), ctypes.byref(out)))
+    return int(out.value)
+
+
+def psf_decorr(obs: PsfObs, l0: float, m0: float, D_ptr: int, stream: int) -> None:
+    _check(lib().psf_decorr(ctypes.byref(obs), l0, m0, D_ptr, stream))
+
+
+def psf_patch(obs: PsfObs, h_src: PsfSrc, D_ptr: Optional[int], prec, P_ptr: int, ws_ptr: int,
+              ws_bytes: int, stream: int) -> None:
+    _check(lib().psf_patch(ctypes.byref(obs), ctypes.byref(h_src), D_ptr, _prec(prec), P_ptr, ws_ptr, ws_bytes,
+                           stream))
+
+
+def psf_patch_batched(obs: PsfObs, h_srcs, d_srcs_ptr: int, prec, tuning_json: Optional[bytes], P_ptr: int,
+                      ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _check(lib().psf_patch_batched(ctypes.byref(obs), len(h_srcs), h_srcs, d_srcs_ptr, _prec(prec), tuning_json,
+                                   P_ptr, ws_ptr, ws_bytes, stream))
+
+
+def psf_patch_backward(obs: PsfObs, h_srcs, d_srcs_ptr: int, G_ptr: int, prec, grad_ptr: int, ws_ptr: int,
+                       ws_bytes: int, stream: int) -> None:
+    _check(lib().psf_patch_backward(ctypes.byref(obs), len(h_srcs), h_srcs, d_srcs_ptr, G_ptr, _prec(prec),
+                                    grad_ptr, ws_ptr, ws_bytes, stream))
+
+
+def psf_autotune(obs: PsfObs, h_srcs, prec, ws_ptr: int, ws_bytes: int, stream: int, cap: int = 1 << 16) -> str:
+    buf = ctypes.create_string_buffer(cap)
+    _check(lib().psf_autotune(ctypes.byref(obs), len(h_srcs), h_srcs, _prec(prec), ws_ptr, ws_bytes, buf, cap,
+                              stream))
+    return buf.value.decode()
+
+
+def psf_timing_enable(on: bool) -> None:
+    _check(lib().psf_timing_enable(1 if on else 0))
+
+
+def psf_timing_read():
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().psf_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- torch layer
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class DeviceObservation:
+    """An observation's arrays resident in device memory, plus the ABI struct.
+
+    ``obs`` is any object with the attributes of ``psf_synth.Observation``
+    (uvw_m, freq_hz, bl_bin, bl_koff, bl_tboff, uvw_c_m, W as numpy arrays).
+    """
+
+    def __init__(self, obs, device="cuda"):
+        torch = _torch()
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt).contiguous().to(device)
+        self.uvw_m = t(obs.uvw_m, torch.float64)
+        self.freq_hz = t(obs.freq_hz, torch.float64)
+        self.bl_bin = t(obs.bl_bin, torch.int32)
+        self.bl_koff = t(obs.bl_koff, torch.int64)
+        self.bl_tboff = t(obs.bl_tboff, torch.int64)
+        self.uvw_c_m = t(obs.uvw_c_m, torch.float64)
+        self.W = t(obs.W, torch.float32)
+        self.n_bl, self.n_t = int(obs.uvw_m.shape[0]), int(obs.uvw_m.shape[1])
+        self.n_ch = int(len(obs.freq_hz))
+        self.K = int(obs.bl_koff[-1])
+        self.n_tb = int(obs.bl_tboff[-1])
+        self.device = device
+        self.struct = PsfObs(self.n_bl, self.n_t, self.n_ch, 0, self.K, self.n_tb, self.uvw_m.data_ptr(),
+                             self.freq_hz.data_ptr(), self.bl_bin.data_ptr(), self.bl_koff.data_ptr(),
+                             self.bl_tboff.data_ptr(), self.uvw_c_m.data_ptr(), self.W.data_ptr())
+
+
+class Workspace:
+    """A growable device scratch buffer for the library's calls."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def workspace_bytes(dobs: DeviceObservation, srcs: Sequence, prec="split_bf16") -> int:
+    return psf_workspace_bytes(dobs.struct, src_array(srcs), prec)
+
+
+def decorr(dobs: DeviceObservation, l0: float, m0: float, out=None):
+    """D_k as a complex64 tensor [K]."""
+    torch = _torch()
+    D = torch.empty((dobs.K, 2), dtype=torch.float32, device=dobs.device) if out is None else out
+    psf_decorr(dobs.struct, float(l0), float(m0), D.data_ptr(), _stream_handle())
+    return torch.view_as_complex(D)
+
+
+def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, workspace: Optional[Workspace] = None):
+    """The distorted PSF patch of one source, float32 [nl, nm]."""
+    torch = _torch()
+    hs = make_src(src)
+    arr = (PsfSrc * 1)(hs)
+    need = psf_workspace_bytes(dobs.struct, arr, prec)
+    ws = (workspace or Workspace(dobs.device)).get(need)
+    P = torch.empty((int(src.nl), int(src.nm)), dtype=torch.float32, device=dobs.device) if out is None else out
+    D_ptr = None
+    if D is not None:
+        Dr = torch.view_as_real(D) if D.is_complex() else D
+        D_ptr = Dr.data_ptr()
+    psf_patch(dobs.struct, hs, D_ptr, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    return P

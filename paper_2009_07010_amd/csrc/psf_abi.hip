@@ -1,0 +1,308 @@
+// Host side of libpsfdecorr: argument validation, workspace planning, launch
+// sequencing and error reporting behind the C ABI declared in include/psf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/psf.h"
+#include "psf_host.hpp"
+#include "psf_kernels.hpp"
+
+namespace psf {
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_msg[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PSF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ device
+int check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  static std::mutex mu;
+  static std::vector<int> state;  // per device: 0 unknown, 1 ok, 2 unsupported
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(state.size()) <= dev) state.resize(dev + 1, 0);
+  if (state[dev] == 0) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    state[dev] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+  }
+  if (state[dev] != 1) return fail(PSF_EUNSUPPORTED, "device %d is not gfx950 (MI355X)", dev);
+  return PSF_OK;
+}
+
+// ------------------------------------------------------------------ validation
+int validate_obs(const psf_obs* o) {
+  if (o == nullptr) return fail(PSF_EINVAL, "obs is NULL");
+  if (o->reserved != 0) return fail(PSF_EINVAL, "obs.reserved must be 0");
+  if (o->n_bl < 0 || o->n_t < 1 || o->n_ch < 1)
+    return fail(PSF_EINVAL, "bad sizes n_bl=%d n_t=%d n_ch=%d", o->n_bl, o->n_t, o->n_ch);
+  if (o->K < 0 || o->n_tb < 0) return fail(PSF_EINVAL, "negative K or n_tb");
+  if (o->n_bl == 0 && (o->K != 0 || o->n_tb != 0)) return fail(PSF_EINVAL, "no baselines but K != 0");
+  if (o->n_bl > 0 && o->K < o->n_bl) return fail(PSF_EINVAL, "K=%lld smaller than n_bl=%d", (long long)o->K, o->n_bl);
+  if (o->n_bl > 0 && (static_cast<int64_t>(o->n_bl) * o->n_t * o->n_ch) < o->K)
+    return fail(PSF_EINVAL, "K exceeds the number of samples");
+  if (o->K > (int64_t(1) << 40)) return fail(PSF_EINVAL, "K too large");
+  if (o->n_bl > 0) {
+    if (!o->uvw_m || !o->freq_hz || !o->bl_bin || !o->bl_koff || !o->bl_tboff || !o->uvw_c_m || !o->W)
+      return fail(PSF_EINVAL, "an observation array pointer is NULL");
+  }
+  return PSF_OK;
+}
+
+int validate_src(const psf_src* s, int idx) {
+  if (s == nullptr) return fail(PSF_EINVAL, "source %d is NULL", idx);
+  if (s->nl < 1 || s->nm < 1 || s->nl > 4096 || s->nm > 4096)
+    return fail(PSF_EINVAL, "source %d: patch %dx%d outside 1..4096", idx, s->nl, s->nm);
+  const double v[6] = {s->l0, s->m0, s->l_first, s->m_first, s->dl, s->dm};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(PSF_EINVAL, "source %d: non-finite direction or grid", idx);
+  if (s->l0 * s->l0 + s->m0 * s->m0 >= 1.0) return fail(PSF_EINVAL, "source %d: l0^2 + m0^2 >= 1", idx);
+  if (s->out_off < 0) return fail(PSF_EINVAL, "source %d: negative out_off", idx);
+  return PSF_OK;
+}
+
+int validate_prec(int prec) {
+  if (prec < PSF_FP32 || prec > PSF_PLAIN_BF16) return fail(PSF_EINVAL, "unknown precision %d", prec);
+  return PSF_OK;
+}
+
+ObsView view(const psf_obs* o) {
+  ObsView v;
+  v.uvw = o->uvw_m;
+  v.freq = o->freq_hz;
+  v.bl_bin = o->bl_bin;
+  v.koff = o->bl_koff;
+  v.tboff = o->bl_tboff;
+  v.uvw_c = o->uvw_c_m;
+  v.W = o->W;
+  v.K = o->K;
+  v.n_tb = o->n_tb;
+  v.n_bl = o->n_bl;
+  v.n_t = o->n_t;
+  v.n_ch = o->n_ch;
+  return v;
+}
+
+// ------------------------------------------------------------------ planning
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
+  const PatchShape sh = patch_shape(prec);
+  PatchPlan p;
+  p.nbi = (s->nl + 15) / 16;
+  p.nbj = (s->nm + 15) / 16;
+  p.tiles_i = (p.nbi + sh.waves_m * sh.blk_m - 1) / (sh.waves_m * sh.blk_m);
+  p.tiles_j = (p.nbj + sh.waves_n * sh.blk_n - 1) / (sh.waves_n * sh.blk_n);
+  const int64_t chunks = (o->K + sh.kchunk - 1) / sh.kchunk;
+  const int tiles = p.tiles_i * p.tiles_j;
+  int64_t n_split = std::max<int64_t>(1, (target_wgs + tiles - 1) / tiles);
+  n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, chunks));
+  const int64_t chunks_per = (chunks + n_split - 1) / n_split;
+  p.k_per_split = std::max<int64_t>(1, chunks_per) * sh.kchunk;
+  p.n_split = static_cast<int>(n_split);
+  p.partial_elems = static_cast<size_t>(p.n_split) * (16 * p.nbi) * (16 * p.nbj);
+  return p;
+}
+
+size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
+  size_t b = 0;
+  b += align_up(static_cast<size_t>(o->K) * sizeof(double2), 256);  // (u', v')
+  b += align_up(static_cast<size_t>(o->K) * sizeof(float2), 256);   // c = W D
+  b += align_up(p.partial_elems * sizeof(float), 256);
+  return b;
+}
+
+// ------------------------------------------------------------------ timing
+namespace {
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0.0;
+  int64_t n = 0;
+} g_timing;
+}  // namespace
+
+bool timing_on() { return g_timing.on; }
+
+hipError_t timed_launch_begin(hipStream_t s, hipEvent_t* ev0) {
+  *ev0 = nullptr;
+  if (!g_timing.on) return hipSuccess;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return hipSuccess;
+  hipError_t e = hipEventCreate(ev0);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(*ev0, s);
+}
+
+hipError_t timed_launch_end(hipStream_t s, hipEvent_t ev0) {
+  if (ev0 == nullptr) return hipSuccess;
+  hipEvent_t ev1;
+  hipError_t e = hipEventCreate(&ev1);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev1, s);
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  g_timing.pending.emplace_back(ev0, ev1);
+  return e;
+}
+
+}  // namespace psf
+
+using namespace psf;
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* psf_version(void) { return "psfdecorr 0.1 gfx950"; }
+
+const char* psf_strerror(int status) {
+  switch (status) {
+    case PSF_OK: return "ok";
+    case PSF_EINVAL: return "invalid argument";
+    case PSF_EWORKSPACE: return "workspace missing or too small";
+    case PSF_EDEVICE: return "HIP device or launch error";
+    case PSF_EUNSUPPORTED: return "unsupported device or feature";
+    default: return "unknown status";
+  }
+}
+
+const char* psf_last_error(void) { return g_msg; }
+
+int psf_timing_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  g_timing.on = on != 0;
+  return PSF_OK;
+}
+
+int psf_timing_read(double* ms_total, int64_t* launches) {
+  if (!ms_total || !launches) return fail(PSF_EINVAL, "NULL output");
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  for (auto& pr : g_timing.pending) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    g_timing.ms += ms;
+    g_timing.n += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  g_timing.pending.clear();
+  *ms_total = g_timing.ms;
+  *launches = g_timing.n;
+  g_timing.ms = 0.0;
+  g_timing.n = 0;
+  return PSF_OK;
+}
+
+int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int prec, size_t* out) {
+  g_msg[0] = 0;
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
+  if (n_src < 1 || h_srcs == nullptr) return fail(PSF_EINVAL, "need n_src >= 1 sources");
+  size_t need = 0;
+  for (int s = 0; s < n_src; ++s) {
+    if ((st = validate_src(&h_srcs[s], s)) != PSF_OK) return st;
+    const PatchPlan p = plan_patch(obs, &h_srcs[s], prec, kTargetWorkgroups);
+    need = std::max(need, patch_workspace(obs, p));
+  }
+  need = std::max(need, batched_workspace(obs, n_src, h_srcs, prec));
+  need = std::max(need, backward_workspace(obs, n_src, h_srcs, prec));
+  *out = need;
+  return PSF_OK;
+}
+
+int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream) {
+  g_msg[0] = 0;
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if (!std::isfinite(l0) || !std::isfinite(m0) || l0 * l0 + m0 * m0 >= 1.0)
+    return fail(PSF_EINVAL, "bad direction (%g, %g)", l0, m0);
+  if (D == nullptr && obs->K > 0) return fail(PSF_EINVAL, "D is NULL");
+  if ((st = check_device()) != PSF_OK) return st;
+  if (obs->K == 0) return PSF_OK;
+  hipError_t e = launch_decorr(view(obs), l0, m0, nullptr, reinterpret_cast<float2*>(D), nullptr, nullptr,
+                               nullptr, nullptr, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_decorr launch");
+}
+
+int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec, float* P, void* ws,
+              size_t ws_bytes, void* stream) {
+  g_msg[0] = 0;
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if ((st = validate_src(h_src, 0)) != PSF_OK) return st;
+  if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if (P == nullptr) return fail(PSF_EINVAL, "P is NULL");
+  const PatchPlan plan = plan_patch(obs, h_src, prec, kTargetWorkgroups);
+  const size_t need = patch_workspace(obs, plan);
+  if (ws == nullptr || ws_bytes < need)
+    return fail(PSF_EWORKSPACE, "psf_patch needs %zu workspace bytes, got %zu", need, ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  double2* uvp = reinterpret_cast<double2*>(w);
+  w += align_up(static_cast<size_t>(obs->K) * sizeof(double2), 256);
+  float2* c = reinterpret_cast<float2*>(w);
+  w += align_up(static_cast<size_t>(obs->K) * sizeof(float2), 256);
+  float* partial = reinterpret_cast<float*>(w);
+
+  hipError_t e = hipSuccess;
+  if (obs->K > 0) {
+    e = launch_decorr(view(obs), h_src->l0, h_src->m0, reinterpret_cast<const float2*>(D), nullptr, uvp, c,
+                      nullptr, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
+  }
+  PatchArgs a;
+  a.uvp = uvp;
+  a.c = c;
+  a.K = obs->K;
+  a.l_first = h_src->l_first;
+  a.dl = h_src->dl;
+  a.l0 = h_src->l0;
+  a.m_first = h_src->m_first;
+  a.dm = h_src->dm;
+  a.m0 = h_src->m0;
+  a.nl = h_src->nl;
+  a.nm = h_src->nm;
+  a.nbi = plan.nbi;
+  a.nbj = plan.nbj;
+  a.tiles_i = plan.tiles_i;
+  a.tiles_j = plan.tiles_j;
+  a.n_split = plan.n_split;
+  a.k_per_split = plan.k_per_split;
+  a.partial = partial;
+  hipEvent_t ev0;
+  if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
+  e = launch_patch(prec, a, s);
+  if (e != hipSuccess) return hip_fail(e, "k_patch launch");
+  if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
+  e = launch_finalize(partial, plan.n_split, plan.nbi, plan.nbj, h_src->nl, h_src->nm, P, s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// Host-side helpers shared by the ABI translation units of libpsfdecorr.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/psf.h"
+#include "psf_kernels.hpp"
+
+namespace psf {
+
+// Workgroups one contraction launch aims for: one per compute unit of an
+// MI355X (256 CUs), the contraction kernels running one workgroup per CU.
+constexpr int kTargetWorkgroups = 256;
+
+struct PatchPlan {
+  int nbi, nbj;
+  int tiles_i, tiles_j;
+  int n_split;
+  int64_t k_per_split;
+  size_t partial_elems;
+};
+
+int fail(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int check_device();
+int validate_obs(const psf_obs* o);
+int validate_src(const psf_src* s, int idx);
+int validate_prec(int prec);
+ObsView view(const psf_obs* o);
+size_t align_up(size_t x, size_t a);
+PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs);
+size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
+
+size_t batched_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
+size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
+
+bool timing_on();
+hipError_t timed_launch_begin(hipStream_t s, hipEvent_t* ev0);
+hipError_t timed_launch_end(hipStream_t s, hipEvent_t ev0);
+
+}  // namespace psf

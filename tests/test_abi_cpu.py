@@ -1,0 +1,123 @@
+"""The C-ABI library builds, loads and exports every declared symbol; host
+validation rejects bad arguments before anything is launched (CPU only:
+no call here reaches the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2009_07010_amd as pk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psf.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pk.LIB_PATH):
+        from paper_2009_07010_amd import build
+        build.build(verbose=False)
+    return pk.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for n in ("psf_decorr", "psf_patch", "psf_patch_batched", "psf_patch_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert name in pk.EXPORTED, f"binding lacks {name}"
+
+
+def test_strerror_and_version(L):
+    for st in (0, -1, -2, -3, -4):
+        assert L.psf_strerror(st)
+    assert b"gfx950" in L.psf_version()
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails validation first
+
+
+def fake_obs(**kw):
+    o = pk.PsfObs(n_bl=3, n_t=10, n_ch=4, reserved=0, K=12, n_tb=6, uvw_m=FAKE, freq_hz=FAKE, bl_bin=FAKE,
+                  bl_koff=FAKE, bl_tboff=FAKE, uvw_c_m=FAKE, W=FAKE)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def fake_src(**kw):
+    s = pk.PsfSrc(l0=0.01, m0=0.02, l_first=0.0, m_first=0.0, dl=1e-5, dm=1e-5, nl=65, nm=65, out_off=0)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def status_of(fn, *args):
+    st = fn(*args)
+    return st, pk.lib().psf_last_error().decode()
+
+
+@pytest.mark.parametrize("bad", [
+    dict(uvw_m=None), dict(W=None), dict(n_t=0), dict(n_ch=-1), dict(K=2), dict(reserved=1),
+    dict(K=10 ** 9),
+])
+def test_bad_observation_rejected(L, bad):
+    o = fake_obs(**bad)
+    srcs = (pk.PsfSrc * 1)(fake_src())
+    out = ctypes.c_size_t(0)
+    st, msg = status_of(L.psf_workspace_bytes, ctypes.byref(o), 1, srcs, 0, ctypes.byref(out))
+    assert st == pk.PSF_EINVAL and msg
+
+
+@pytest.mark.parametrize("bad", [dict(nl=0), dict(nm=5000), dict(l0=0.9, m0=0.9), dict(dl=float("nan")),
+                                 dict(out_off=-1)])
+def test_bad_source_rejected(L, bad):
+    o = fake_obs()
+    s = fake_src(**bad)
+    st, msg = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 0, FAKE, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL and msg
+
+
+def test_bad_precision_and_null_output(L):
+    o, s = fake_obs(), fake_src()
+    st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 7, FAKE, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 0, None, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL
+
+
+def test_workspace_too_small(L):
+    o, s = fake_obs(), fake_src()
+    srcs = (pk.PsfSrc * 1)(s)
+    need = ctypes.c_size_t(0)
+    assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, 1, ctypes.byref(need)) == 0
+    assert need.value > 12 * 24
+    st, msg = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, FAKE, need.value - 1, None)
+    assert st == pk.PSF_EWORKSPACE and "workspace" in msg
+    st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, None, need.value, None)
+    assert st == pk.PSF_EWORKSPACE
+
+
+def test_decorr_bad_direction(L):
+    o = fake_obs()
+    st, _ = status_of(L.psf_decorr, ctypes.byref(o), 0.8, 0.8, FAKE, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_decorr, ctypes.byref(o), float("inf"), 0.0, FAKE, None)
+    assert st == pk.PSF_EINVAL
+
+
+def test_binding_raises_on_error(L):
+    with pytest.raises(pk.PsfError) as ei:
+        pk.psf_decorr(fake_obs(n_t=0), 0.0, 0.0, FAKE, 0)
+    assert ei.value.status == pk.PSF_EINVAL

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar: peak-normalised max error <= 1e-5 for the FP32 and split forms (the
+target error of the PSF patches), D_k within FP32 rounding of the oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import psf_synth as ps
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2009_07010_amd as pk  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-5
+ACCURATE = ["fp32", "split_bf16", "split_fp16"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.lib()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    obs = ps.observation(1)
+    src = ps.sources(1)[0]
+    D = orc.decorr(obs, src.l0, src.m0)
+    P = orc.patch_factored(obs, src, D)
+    return obs, pk.DeviceObservation(obs), src, D, P
+
+
+def gpu_patch(dobs, src, prec, D=None):
+    P = pk.patch(dobs, src, prec=prec, D=D)
+    torch.cuda.synchronize()
+    return P.double().cpu().numpy()
+
+
+def test_decorr_config1(cfg1):
+    obs, dobs, src, D, _ = cfg1
+    Dg = pk.decorr(dobs, src.l0, src.m0)
+    torch.cuda.synchronize()
+    Dg = Dg.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(Dg - D)) < 2e-6
+
+
+@pytest.mark.parametrize("prec", ACCURATE)
+def test_patch_config1(cfg1, prec):
+    obs, dobs, src, D, P = cfg1
+    Pg = gpu_patch(dobs, src, prec)
+    err, rms = orc.peak_normalised_error(Pg, P)
+    print(f"config1 {prec}: max {err:.3e} rms {rms:.3e}")
+    assert err < TOL
+
+
+@pytest.mark.parametrize("prec", ACCURATE)
+def test_patch_config1_given_D(cfg1, prec):
+    obs, dobs, src, D, P = cfg1
+    Dt = torch.as_tensor(D.astype(np.complex64)).cuda()
+    Pg = gpu_patch(dobs, src, prec, D=Dt)
+    assert orc.peak_normalised_error(Pg, P)[0] < TOL
+
+
+def test_plain_bf16_negative_control(cfg1):
+    # one BF16 product per term (no split) misses the bar at this size
+    obs, dobs, src, D, P = cfg1
+    Pg = gpu_patch(dobs, src, "plain_bf16")
+    err = orc.peak_normalised_error(Pg, P)[0]
+    print(f"config1 plain_bf16: max {err:.3e}")
+    assert err > TOL
+
+
+def test_config1_twenty_sample_bins():
+    obs = ps.observation(1, bin_samples=20)
+    assert obs.K == 630
+    src = ps.sources(1)[0]
+    P = orc.patch_factored(obs, src)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ACCURATE:
+        assert orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0] < TOL
+
+
+@pytest.mark.parametrize("n,nm", [(1, 1), (2, 3), (17, 17), (33, 16), (65, 129), (129, 129), (160, 161),
+                                  (257, 257)])
+def test_patch_sizes(n, nm):
+    obs = ps.tiny_random(31, n_ant=6, n_t=40, n_ch=6, nt=7, nc=4, radius_m=4000.0)
+    src = ps.Source.centred(0.012, -0.021, n, 1.5 * ps.ARCSEC, nm=nm)
+    P = orc.patch_factored(obs, src)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ACCURATE:
+        err = orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0]
+        assert err < TOL, (prec, err)
+
+
+# Worst-case error of one split-BF16 term relative to |a||b|: each operand
+# keeps hi + lo = 16 significant bits, |lo| <= 2^-8 |v|, and the dropped
+# lo*lo product and the rounding of both lo parts each contribute up to
+# 2^-16, so 3 * 2^-16 ~ 4.6e-5.  With many bins the sign-random term errors
+# average far below 1e-5; a lone bin sees the per-term bound.
+SPLIT_BF16_TERM_BOUND = 3 * 2.0 ** -16
+
+
+def test_single_bin_observation():
+    obs = ps.make_observation(np.array([[0.0, 0.0, 0.0], [1200.0, -800.0, 3.0]]), 5, 2.0,
+                              ps.channel_centres(1.3e9, 1.31e9, 3), [5, 3])
+    assert obs.K == 1
+    src = ps.Source.centred(0.02, 0.01, 65, 2 * ps.ARCSEC)
+    P = orc.patch_factored(obs, src)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ACCURATE:
+        err = orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0]
+        print(f"K=1 {prec}: {err:.3e}")
+        assert err < (SPLIT_BF16_TERM_BOUND if prec == "split_bf16" else TOL), (prec, err)
+
+
+def test_ragged_bda_bins_and_long_k():
+    obs = ps.tiny_random(32, n_ant=12, n_t=37, n_ch=7, nt=8, nc=3, radius_m=4000.0, bda=True)
+    src = ps.Source.centred(-0.015, 0.02, 65, 1.5 * ps.ARCSEC)
+    D = orc.decorr(obs, src.l0, src.m0)
+    P = orc.patch_factored(obs, src, D)
+    dobs = pk.DeviceObservation(obs)
+    Dg = pk.decorr(dobs, src.l0, src.m0).cpu().numpy()
+    assert np.max(np.abs(Dg - D)) < 2e-6
+    for prec in ACCURATE:
+        assert orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0] < TOL
+
+
+def test_single_sample_bins_and_phase_centre():
+    obs = ps.tiny_random(33, n_ant=5, n_t=6, n_ch=2, nt=1, nc=1)
+    dobs = pk.DeviceObservation(obs)
+    Dg = pk.decorr(dobs, 0.03, -0.02).cpu().numpy()
+    assert np.all(Dg == 1.0 + 0.0j)
+    obs1 = ps.observation(1)
+    D0 = pk.decorr(pk.DeviceObservation(obs1), 0.0, 0.0).cpu().numpy()
+    assert np.all(D0 == 1.0 + 0.0j)
+
+
+def test_zero_weights_give_zero_patch():
+    obs = ps.tiny_random(34, n_ant=4, n_t=9, n_ch=3, nt=3, nc=2)
+    obs.W[:] = 0.0
+    src = ps.Source.centred(0.01, 0.01, 33, 2 * ps.ARCSEC)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ACCURATE:
+        assert np.all(gpu_patch(dobs, src, prec) == 0.0)
+
+
+def test_repeat_calls_bitwise_identical(cfg1):
+    obs, dobs, src, D, P = cfg1
+    a = gpu_patch(dobs, src, "split_bf16")
+    b = gpu_patch(dobs, src, "split_bf16")
+    assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    path = os.path.join(HERE, "golden", "config2_seed0_P.npy")
+    if not os.path.exists(path):
+        pytest.skip("config-2 golden patch not generated")
+    obs = ps.observation(2, seed=0)
+    src = ps.sources(2, seed=0)[0]
+    return obs, pk.DeviceObservation(obs), src, np.load(path)
+
+
+@pytest.mark.parametrize("prec", ACCURATE)
+def test_config2_full_patch(cfg2, prec):
+    obs, dobs, src, P = cfg2
+    Pg = gpu_patch(dobs, src, prec)
+    err, rms = orc.peak_normalised_error(Pg, P)
+    print(f"config2 {prec}: max {err:.3e} rms {rms:.3e}")
+    assert err < TOL
+
+
+def test_config2_decorr_sample(cfg2):
+    obs, dobs, src, _ = cfg2
+    smp = np.load(os.path.join(HERE, "golden", "config2_seed0_Dsample.npy"))
+    ks = smp[:, 0].astype(np.int64)
+    Dref = smp[:, 1] + 1j * smp[:, 2]
+    Dg = pk.decorr(dobs, src.l0, src.m0).cpu().numpy()[ks]
+    assert np.max(np.abs(Dg - Dref)) < 2e-6
