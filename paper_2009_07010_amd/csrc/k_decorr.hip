@@ -48,17 +48,17 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
     dim = d.y;
   } else {
     const bool grad = dDl_out != nullptr;
-    const double A_k = __dadd_rn(__dadd_rn(__dmul_rn(uc, l0), __dmul_rn(vc, m0)), __dmul_rn(wc, Lw));
-    const double A_knu = __dmul_rn(A_k, nu_k);
+    const double A_k = uc * l0 + vc * m0 + wc * Lw;
+    const double A_knu = A_k * nu_k;
     float sre = 0.f, sim = 0.f;
     float glr = 0.f, gli = 0.f, gmr = 0.f, gmi = 0.f;
     const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
     for (int t = r.t0; t < r.t1; ++t) {
       const double u = row[3 * t + 0], v = row[3 * t + 1], w = row[3 * t + 2];
-      const double A_t = __dadd_rn(__dadd_rn(__dmul_rn(u, l0), __dmul_rn(v, m0)), __dmul_rn(w, Lw));
+      const double A_t = u * l0 + v * m0 + w * Lw;
       for (int c = r.c0; c < r.c1; ++c) {
         const double nu = o.freq[c];
-        const double phi = __dmul_rn(__dsub_rn(__dmul_rn(A_t, nu), A_knu), kInvCLight);
+        const double phi = (A_t * nu - A_knu) * kInvCLight;
         const cf32 e = expi_turns(-phi);
         sre += e.re;
         sim += e.im;

@@ -2,6 +2,7 @@
 // sequencing and error reporting behind the C ABI declared in include/psf.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,21 +107,28 @@ ObsView view(const psf_obs* o) {
 // ------------------------------------------------------------------ planning
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
-  const PatchShape sh = patch_shape(prec);
+PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int /*prec*/, int target_wgs) {
   PatchPlan p;
-  p.nbi = (s->nl + 15) / 16;
-  p.nbj = (s->nm + 15) / 16;
-  p.tiles_i = (p.nbi + sh.waves_m * sh.blk_m - 1) / (sh.waves_m * sh.blk_m);
-  p.tiles_j = (p.nbj + sh.waves_n * sh.blk_n - 1) / (sh.waves_n * sh.blk_n);
-  const int64_t chunks = (o->K + sh.kchunk - 1) / sh.kchunk;
-  const int tiles = p.tiles_i * p.tiles_j;
-  int64_t n_split = std::max<int64_t>(1, (target_wgs + tiles - 1) / tiles);
-  n_split = std::min<int64_t>(n_split, std::max<int64_t>(1, chunks));
-  const int64_t chunks_per = (chunks + n_split - 1) / n_split;
-  p.k_per_split = std::max<int64_t>(1, chunks_per) * sh.kchunk;
-  p.n_split = static_cast<int>(n_split);
-  p.partial_elems = static_cast<size_t>(p.n_split) * (16 * p.nbi) * (16 * p.nbj);
+  TilePlan& t = p.tp;
+  plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
+  const int64_t chunks = std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk);
+  // k-slices per tile in proportion to the cost of one chunk of that tile
+  // (the block count of its largest wave), so that workgroups take alike
+  const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
+  double cost[2][2], work = 0.0;
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      cost[r][c] = ((t.tbi[r] + 1) / 2) * ((t.tbj[c] + 1) / 2);
+      work += static_cast<double>(cnt_i[r]) * cnt_j[c] * cost[r][c];
+    }
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      int64_t n = static_cast<int64_t>(std::llround(target_wgs * cost[r][c] / work));
+      n = std::min<int64_t>(std::max<int64_t>(1, n), chunks);
+      t.ns[r][c] = static_cast<int>(n);
+      t.kps[r][c] = ((chunks + n - 1) / n) * kPatchChunk;
+    }
+  p.partial_elems = tile_plan_partial_elems(t);
   return p;
 }
 
@@ -289,19 +297,15 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
   a.m0 = h_src->m0;
   a.nl = h_src->nl;
   a.nm = h_src->nm;
-  a.nbi = plan.nbi;
-  a.nbj = plan.nbj;
-  a.tiles_i = plan.tiles_i;
-  a.tiles_j = plan.tiles_j;
-  a.n_split = plan.n_split;
-  a.k_per_split = plan.k_per_split;
+  a.tp = plan.tp;
+  a.flush_chunks = kFlushChunks;
   a.partial = partial;
   hipEvent_t ev0;
   if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
   e = launch_patch(prec, a, s);
   if (e != hipSuccess) return hip_fail(e, "k_patch launch");
   if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_finalize(partial, plan.n_split, plan.nbi, plan.nbj, h_src->nl, h_src->nm, P, s);
+  e = launch_finalize(a, P, s);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
 }
 

@@ -1,9 +1,8 @@
 // Device-side building blocks shared by the kernels of libpsfdecorr (gfx950).
 //
 // Phase factors exp(2 pi i theta) with theta in turns: theta is formed in
-// FP64 (u' x reaches tens of turns, u l0 thousands), reduced to its
-// fractional part in FP64 -- exact, since subtracting the nearest integer
-// loses nothing -- and only then converted to FP32 for sin/cos.
+// FP64 (u' x reaches tens of turns, u l0 thousands) and reduced to a
+// fraction of a turn in FP64; only the reduced angle goes to FP32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
@@ -22,19 +21,29 @@ __device__ __forceinline__ cf32 cmul(cf32 a, cf32 b) {
 }
 __device__ __forceinline__ cf32 conj(cf32 a) { return {a.re, -a.im}; }
 
-// Fractional part of theta (turns) in [-1/2, 1/2], computed in FP64.
-__device__ __forceinline__ double reduce_turns(double theta) { return theta - rint(theta); }
-
-// exp(2 pi i r) for |r| <= 1/2 turns, FP32.
-__device__ __forceinline__ cf32 expi_turns_f32(float r) {
-  float s, c;
-  sincospif(2.0f * r, &s, &c);
-  return {c, s};
-}
-
-// exp(2 pi i theta): FP64 argument reduction, FP32 evaluation.
+// exp(2 pi i theta) for theta in turns.
+//
+// FP64 step: q = nearest quarter turn, r = theta - q/4 with |r| <= 1/8 turn
+// (q/4 is exact, so r carries the full FP64 accuracy of theta's fraction).
+// FP32 step: x = 2 pi r in [-pi/4, pi/4]; sin and cos from their Taylor
+// series through x^9 and x^10 (truncation below 2e-9, under FP32 rounding);
+// the quadrant q mod 4 rotates (cos, sin) by multiples of 90 degrees.
 __device__ __forceinline__ cf32 expi_turns(double theta) {
-  return expi_turns_f32(static_cast<float>(reduce_turns(theta)));
+  const double q = rint(4.0 * theta);
+  const double r = fma(-0.25, q, theta);
+  const float x = static_cast<float>(r * 6.283185307179586);
+  const float x2 = x * x;
+  // coefficients (-1)^n / (2n+1)! and (-1)^n / (2n)!
+  constexpr float s3 = -1.0f / 6.0f, s5 = 1.0f / 120.0f, s7 = -1.0f / 5040.0f, s9 = 1.0f / 362880.0f;
+  constexpr float c2 = -0.5f, c4 = 1.0f / 24.0f, c6 = -1.0f / 720.0f, c8 = 1.0f / 40320.0f,
+                  c10 = -1.0f / 3628800.0f;
+  const float s = x * (1.0f + x2 * (s3 + x2 * (s5 + x2 * (s7 + x2 * s9))));
+  const float c = 1.0f + x2 * (c2 + x2 * (c4 + x2 * (c6 + x2 * (c8 + x2 * c10))));
+  const int quad = static_cast<int>(static_cast<long long>(q) & 3);
+  cf32 z;
+  z.re = (quad == 0) ? c : (quad == 1) ? -s : (quad == 2) ? -c : s;
+  z.im = (quad == 0) ? s : (quad == 1) ? c : (quad == 2) ? -s : -c;
+  return z;
 }
 
 // Index of the baseline that owns bin k: largest b with koff[b] <= k.
@@ -81,25 +90,27 @@ __device__ __forceinline__ double bin_freq(const double* __restrict__ freq, int 
   return s / static_cast<double>(c1 - c0);
 }
 
-// Pack helpers for the split forms: hi = round(x), lo = round(x - hi).
+// Pack helpers for the split forms: two floats -> two round-to-nearest
+// 16-bit values in one register (one hardware conversion each pair).
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  __bf16 ha = static_cast<__bf16>(a), hb = static_cast<__bf16>(b);
-  uint16_t ua = __builtin_bit_cast(uint16_t, ha), ub = __builtin_bit_cast(uint16_t, hb);
-  return static_cast<uint32_t>(ua) | (static_cast<uint32_t>(ub) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
 }
+// the two halves of a packed bf16 pair, widened back to float (exact)
 __device__ __forceinline__ float bf16_lo_to_f32(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
 __device__ __forceinline__ float bf16_hi_to_f32(uint32_t p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
 
 __device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
-  _Float16 ha = static_cast<_Float16>(a), hb = static_cast<_Float16>(b);
-  uint16_t ua = __builtin_bit_cast(uint16_t, ha), ub = __builtin_bit_cast(uint16_t, hb);
-  return static_cast<uint32_t>(ua) | (static_cast<uint32_t>(ub) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, f16x2_t));
 }
 __device__ __forceinline__ float f16_lo_to_f32(uint32_t p) {
-  return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(p & 0xffffu)));
+  return static_cast<float>(__builtin_bit_cast(f16x2_t, p)[0]);
 }
 __device__ __forceinline__ float f16_hi_to_f32(uint32_t p) {
-  return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(p >> 16)));
+  return static_cast<float>(__builtin_bit_cast(f16x2_t, p)[1]);
 }
 
 }  // namespace psf

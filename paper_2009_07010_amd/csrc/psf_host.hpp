@@ -12,12 +12,12 @@ namespace psf {
 // Workgroups one contraction launch aims for: one per compute unit of an
 // MI355X (256 CUs), the contraction kernels running one workgroup per CU.
 constexpr int kTargetWorkgroups = 256;
+// First-level accumulation run of the contraction: 32 chunks of 16
+// visibilities (512 terms per pixel) before folding into the second level.
+constexpr int kFlushChunks = 32;
 
 struct PatchPlan {
-  int nbi, nbj;
-  int tiles_i, tiles_j;
-  int n_split;
-  int64_t k_per_split;
+  TilePlan tp;
   size_t partial_elems;
 };
 

@@ -21,36 +21,45 @@ struct ObsView {
 
 enum Prec : int { kFP32 = 0, kSplitBF16 = 1, kSplitFP16 = 2, kPlainBF16 = 3 };
 
+// Tiling of one patch.  Row tiles come in two heights (ti_a tiles of tbi[0]
+// blocks, then ti_b tiles of tbi[1]), column tiles in two widths (tj_a of
+// tbj[0], then tj_b of tbj[1]); a 16x16 block is the unit.  Each tile type
+// (row type r, column type c) gets ns[r][c] k-slices of kps[r][c]
+// visibilities.  Workgroups, and the partial slabs they write
+// ([16 tbi][16 tbj] floats each), are numbered tile by tile in row-major
+// tile order, slice by slice within a tile.
+struct TilePlan {
+  int tbi[2], tbj[2];
+  int ti_a, ti_b, tj_a, tj_b;
+  int ns[2][2];
+  int64_t kps[2][2];
+};
+
 // One source's patch contraction over precomputed per-bin records.
 struct PatchArgs {
-  const double2* uvp;    // [K] (u'_k, v'_k) in wavelengths
-  const float2* c;       // [K] W_k D_k
+  const double2* uvp;        // [K] (u'_k, v'_k) in wavelengths
+  const float2* c;           // [K] W_k D_k
   int64_t K;
   double l_first, dl, l0;
   double m_first, dm, m0;
-  int nl, nm;            // patch size
-  int nbi, nbj;          // 16-pixel blocks along l and m
-  int tiles_i, tiles_j;  // tiles of the patch, each handled by one workgroup per k-slice
-  int n_split;           // k-slices
-  int64_t k_per_split;   // multiple of the chunk length
-  float* partial;        // [n_split][16 nbi][16 nbj]
+  int nl, nm;                // patch size
+  TilePlan tp;
+  int flush_chunks;          // chunks per first-level (matrix-core) accumulation run
+  float* partial;            // partial slabs, see TilePlan
 };
 
-// Geometry of a contraction kernel instance (compile-time constants exposed
-// to the host planner).
-struct PatchShape {
-  int waves_m, waves_n;    // wave grid of a workgroup
-  int blk_m, blk_n;        // max 16x16 blocks per wave
-  int kchunk;              // visibilities per LDS chunk
-};
+constexpr int kPatchChunk = 16;  // visibilities per contraction chunk
 
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
                          double2* uvp_out, float2* c_out, float2* dDl_out, float2* dDm_out,
                          hipStream_t stream);
 
-PatchShape patch_shape(int prec);
+// Tile shapes of the compiled contraction for a patch of nbi x nbj blocks;
+// fills tbi, tbj and the tile counts of *tp (not ns / kps).
+void plan_tiles(int nbi, int nbj, TilePlan* tp);
+int64_t tile_plan_workgroups(const TilePlan& tp);
+size_t tile_plan_partial_elems(const TilePlan& tp);
 hipError_t launch_patch(int prec, const PatchArgs& a, hipStream_t stream);
-hipError_t launch_finalize(const float* partial, int n_split, int nbi, int nbj, int nl, int nm,
-                           float* P, hipStream_t stream);
+hipError_t launch_finalize(const PatchArgs& a, float* P, hipStream_t stream);
 
 }  // namespace psf
