@@ -11,27 +11,32 @@
 // k-slice, keeps the tile in matrix-core accumulators, and writes a partial
 // tile; K-f adds the partials in slice order (deterministic).
 //
-// Per chunk of 16 visibilities a workgroup of 4 waves
-//   * generates the chunk's A and B columns for its tile into one of two LDS
-//     buffers, in the exact operand layout of the MFMA instruction (K-b), and
-//   * contracts the other buffer's chunk with matrix-core instructions (K-c),
-// so one barrier per chunk separates writers from readers.  Each thread of
-// the generator owns one visibility and one run of R consecutive rows: one
-// FP64-reduced seed exp(2 pi i u' x_run) and one FP64-reduced step
-// exp(2 pi i u' dl), then FP32 complex multiplication along the run.
+// A workgroup has 8 waves: 4 contraction waves and 4 generator waves, one
+// of each per SIMD, so the matrix core (contraction) and the vector ALU
+// (phase factors) of a SIMD work at the same time.  Per chunk of 16
+// visibilities
+//   * the generator waves write the next chunk's A and B columns for the
+//     tile into one of two LDS buffers, in the exact operand layout of the
+//     MFMA instruction (K-b), and
+//   * the contraction waves run the MFMAs of the current chunk from the
+//     other buffer (K-c),
+// and one barrier per chunk separates writers from readers.  Each generator
+// thread owns one visibility and every 8th row of A or of B: one FP64-reduced
+// seed exp(2 pi i u' x_r0) and one FP64-reduced step exp(2 pi i u' 8 dl),
+// then FP32 complex multiplication along the rows.
 //
 // Tile and wave shapes are compile-time: a tile of TBI x TBJ 16x16 blocks is
-// cut into a 2 x 2 grid of wave sub-tiles whose block counts differ by at
-// most one; each wave runs the loop instantiated for its own shape (chosen
-// by a uniform switch on the wave index), so the contraction is straight-line
-// code with no per-block conditions.
+// cut into a 2 x 2 grid of contraction-wave sub-tiles whose block counts
+// differ by at most one; each wave runs the loop instantiated for its own
+// shape (chosen by a uniform switch on the wave index), so the contraction
+// is straight-line code with no per-block conditions.
 //
 // Two-level accumulation: matrix-core accumulators collect a run of
-// flush_chunks chunks and are then added into a second FP32 tile held in
-// registers.  A single FP32 accumulator over a whole k-slice loses up to
-// ~2e-5 of the peak at pixels where many nearly equal terms add up (the
-// rounding of a long sum of similar increments is coherent); short runs
-// keep each rounding small relative to the final value.
+// flush_chunks chunks and are then added into a second FP32 tile kept in
+// LDS.  A single FP32 accumulator over a whole k-slice loses up to ~2e-5 of
+// the peak at pixels where many nearly equal terms add up (the rounding of a
+// long sum of similar increments is coherent); short runs keep each
+// rounding small relative to the final value.
 //
 // Split forms: every operand value v is stored as hi = round16(v) and
 // lo = round16(v - hi); the product uses hi*hi + hi*lo + lo*hi (three MFMAs)
@@ -49,19 +54,18 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) uint8_t lds_t;
 
 // One LDS operand row: 32 16-bit values (16 visibilities x re/im) or, per
-// group of 8 visibilities, 16 floats: 64 bytes, padded to 80 so that 8
-// consecutive rows read with 16-byte loads touch 32 distinct banks.
-constexpr int kRowBytes = 80;
-constexpr int kChunk = 16;  // visibilities per LDS chunk
+// group of 8 visibilities, 16 floats: 64 bytes, i.e. half of the 32 banks.
+// The four 16-byte chunks of row r are stored XOR-swizzled by (r >> 1) & 3,
+// which makes the 16-byte operand reads of 8 consecutive rows hit 32
+// distinct banks.  A generator thread writes the rows of one residue class
+// mod 8 (rows r0, r0 + 8, ...), so its swizzle is constant, and the two
+// 16-lane groups of a half-wave write adjacent rows, i.e. opposite bank
+// halves.
+constexpr int kRowBytes = 64;
+constexpr int kChunk = 16;    // visibilities per LDS chunk
+constexpr int kPrefetch = 4;  // chunks of per-bin records held ahead by a generator thread
 
-// Generator geometry of a tile of TI x TJ pixels: run length R such that the
-// A runs and B runs together number at most 16 (16 runs x 16 visibilities =
-// 256 threads).
-constexpr int gen_run(int TI, int TJ) {
-  int R = (TI + TJ + 15) / 16;
-  while ((TI + R - 1) / R + (TJ + R - 1) / R > 16) ++R;
-  return R;
-}
+__device__ __forceinline__ int swz(int row, int chunk) { return (chunk ^ ((row >> 1) & 3)) << 4; }
 
 template <int PREC>
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, f32x4 acc) {
@@ -81,13 +85,16 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, f32x4 
 // i.e. visibilities 4g..4g+3 as (re, im) pairs.
 template <int PREC>
 __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int gstride, int row, int v, cf32 z) {
+  typedef __attribute__((address_space(3))) float lds_f32;
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
   if constexpr (PREC == kFP32) {
     const int g = v >> 3, kv = v & 7;
-    lds_t* p = hi_plane + g * gstride + row * kRowBytes + (kv & 1) * 32 + (kv >> 1) * 4;
-    *reinterpret_cast<__attribute__((address_space(3))) float*>(p) = z.re;
-    *reinterpret_cast<__attribute__((address_space(3))) float*>(p + 16) = z.im;
+    const int slot = (kv & 1) * 2;
+    lds_t* base = hi_plane + g * gstride + row * kRowBytes + (kv >> 1) * 4;
+    *reinterpret_cast<lds_f32*>(base + swz(row, slot)) = z.re;
+    *reinterpret_cast<lds_f32*>(base + swz(row, slot + 1)) = z.im;
   } else {
-    lds_t* p = hi_plane + row * kRowBytes + v * 4;
+    lds_t* p = hi_plane + row * kRowBytes + swz(row, v >> 2) + (v & 3) * 4;
     uint32_t hi, lo = 0;
     if constexpr (PREC == kSplitFP16) {
       hi = pack_f16x2(z.re, z.im);
@@ -96,108 +103,58 @@ __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int g
       hi = pack_bf16x2(z.re, z.im);
       if constexpr (PREC == kSplitBF16) lo = pack_bf16x2(z.re - bf16_lo_to_f32(hi), z.im - bf16_hi_to_f32(hi));
     }
-    *reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(p) = hi;
-    if constexpr (PREC != kPlainBF16) *reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(p + lo_off) = lo;
+    *reinterpret_cast<lds_u32*>(p) = hi;
+    if constexpr (PREC != kPlainBF16) *reinterpret_cast<lds_u32*>(p + lo_off) = lo;
   }
 }
 
-// LDS geometry of one tile type.
+// LDS geometry of one tile type: two operand buffers and the second-level
+// accumulator tile of the four contraction waves.
 template <int PREC, int TBI, int TBJ>
 struct TileGeom {
   static constexpr int TI = 16 * TBI, TJ = 16 * TBJ;
-  static constexpr int R = gen_run(TI, TJ);
-  static constexpr int NA = (TI + R - 1) / R, NB = (TJ + R - 1) / R;
-  static constexpr int ROWS_A = NA * R, ROWS_B = NB * R;  // rows written (>= TI, TJ)
+  static constexpr int RA = TI / 8, RB = TJ / 8;  // rows per generator thread (stride 8)
   static constexpr bool F32 = PREC == kFP32;
   static constexpr bool TWO = PREC == kSplitBF16 || PREC == kSplitFP16;
-  static constexpr int GA = ROWS_A * kRowBytes, GB = ROWS_B * kRowBytes;  // one group / plane
+  static constexpr int GA = TI * kRowBytes, GB = TJ * kRowBytes;  // one group / plane
   static constexpr int APL = (F32 ? 2 : 1) * GA, BPL = (F32 ? 2 : 1) * GB;
   static constexpr int NPL = TWO ? 2 : 1;
   static constexpr int BUF = NPL * (APL + BPL);
-  static constexpr int LDS = 2 * BUF;
+  static constexpr int TOT = TBI * TBJ * 1024;  // per 16x16 block: 64 lanes x 4 floats
+  static constexpr int LDS = 2 * BUF + TOT;
+  // wave sub-tiles: rows M0 then M1 blocks, columns N0 then N1
+  static constexpr int M0 = (TBI + 1) / 2, M1 = TBI / 2, N0 = (TBJ + 1) / 2, N1 = TBJ / 2;
 };
 
-// The whole k-loop of one wave whose sub-tile is M x N blocks starting at
-// block (WI0, WJ0) of the tile.
+// Contraction wave: sub-tile of M x N blocks at block (WI0, WJ0) of the
+// tile; its second-level accumulators live in LDS at tot (block-major, in
+// accumulator lane order).
 template <int PREC, int TBI, int TBJ, int M, int N, int WI0, int WJ0>
-__device__ __forceinline__ void wave_loop(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
-                                          int64_t ke, float* __restrict__ out, int width) {
+__device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, lds_t* tot, int64_t nch,
+                                          float* __restrict__ out, int width) {
   using G = TileGeom<PREC, TBI, TBJ>;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+  typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
+  const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
+  const int rd = swz(lr, lg);  // swizzled chunk of this lane's operand reads (row = 16 b + lr)
+  lds_f32x4* my_tot = reinterpret_cast<lds_f32x4*>(tot) + lane;
 
-  // generator role: visibility gv of each chunk, run grho of A rows then B rows
-  const int gv = tid & 15, grho = tid >> 4;
-  const bool gA = grho < G::NA;
-  const bool gact = grho < G::NA + G::NB;
-  const int grow0 = (gA ? grho : grho - G::NA) * G::R;
-  const double gpos0 = gA ? (a.l_first + (16 * bi0 + grow0) * a.dl) - a.l0
-                          : (a.m_first + (16 * bj0 + grow0) * a.dm) - a.m0;
-  const double gd = gA ? a.dl : a.dm;
-  const int gstride = gA ? G::GA : G::GB;
-  const int goff = gA ? 0 : G::NPL * G::APL;
-  const int glo = gA ? G::APL : G::BPL;
-
-  auto fetch = [&](int64_t n, double& f, cf32& cc) {
-    f = 0.0;
-    cc = {0.f, 0.f};
-    const int64_t kg = kb + n * kChunk + gv;
-    if (gact && kg < ke) {
-      const double2 uv = a.uvp[kg];
-      f = gA ? uv.x : uv.y;
-      const float2 c = a.c[kg];
-      cc = {c.x, c.y};
-    }
-  };
-  auto generate = [&](int buf, double f, cf32 cc) {
-    if (!gact) return;
-    cf32 z = expi_turns(f * gpos0);
-    cf32 zs = expi_turns(f * gd);
-    if (gA) {
-      z = conj(cmul(cc, z));
-      zs = conj(zs);
-    }
-    lds_t* plane = smem + buf * G::BUF + goff;
-#pragma unroll
-    for (int q = 0; q < G::R; ++q) {
-      store_operand<PREC>(plane, glo, gstride, grow0 + q, gv, z);
-      z = cmul(z, zs);
-    }
-  };
-
-  f32x4 acc[M][N], tot[M][N];
+  f32x4 acc[M][N];
 #pragma unroll
   for (int r = 0; r < M; ++r)
 #pragma unroll
     for (int c = 0; c < N; ++c) {
       acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-      tot[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+      my_tot[(r * N + c) * 64] = acc[r][c];
     }
+  __syncthreads();  // chunk 0 generated
 
-  if (nch > 0) {
-    double f;
-    cf32 cc;
-    fetch(0, f, cc);
-    generate(0, f, cc);
-  }
-  __syncthreads();
-
-  // Runs of flush_chunks chunks: matrix-core accumulators within a run, the
-  // second-level tile between runs.  The last chunk also generates a chunk
-  // past the end (all-zero weights) into the idle buffer; nothing reads it.
   const int64_t flush = a.flush_chunks;
   for (int64_t run0 = 0; run0 < nch; run0 += flush) {
     const int64_t run1 = min(nch, run0 + flush);
     for (int64_t n = run0; n < run1; ++n) {
-      const int cur = static_cast<int>(n & 1);
-      double fn;
-      cf32 ccn;
-      fetch(n + 1, fn, ccn);
-
-      // ---- K-c / K-e: contract the current chunk
-      const lds_t* Ah = smem + cur * G::BUF;
+      const lds_t* Ah = smem + static_cast<int>(n & 1) * G::BUF;
       const lds_t* Bh = Ah + G::NPL * G::APL;
       if constexpr (G::F32) {
 #pragma unroll
@@ -205,12 +162,11 @@ __device__ __forceinline__ void wave_loop(const PatchArgs& a, lds_t* smem, int b
           f32x4 av[M];
 #pragma unroll
           for (int r = 0; r < M; ++r)
-            av[r] = *reinterpret_cast<const __attribute__((address_space(3))) f32x4*>(
-                Ah + g * G::GA + (16 * (WI0 + r) + lr) * kRowBytes + lg * 16);
+            av[r] = *reinterpret_cast<const lds_f32x4*>(Ah + g * G::GA + (16 * (WI0 + r) + lr) * kRowBytes + rd);
 #pragma unroll
           for (int c = 0; c < N; ++c) {
-            const f32x4 bv = *reinterpret_cast<const __attribute__((address_space(3))) f32x4*>(
-                Bh + g * G::GB + (16 * (WJ0 + c) + lr) * kRowBytes + lg * 16);
+            const f32x4 bv =
+                *reinterpret_cast<const lds_f32x4*>(Bh + g * G::GB + (16 * (WJ0 + c) + lr) * kRowBytes + rd);
 #pragma unroll
             for (int r = 0; r < M; ++r)
 #pragma unroll
@@ -222,17 +178,16 @@ __device__ __forceinline__ void wave_loop(const PatchArgs& a, lds_t* smem, int b
         bf16x8 ah[M], al[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-          const int off = (16 * (WI0 + r) + lr) * kRowBytes + lg * 16;
-          ah[r] = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(Ah + off);
-          if constexpr (G::TWO)
-            al[r] = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(Ah + G::APL + off);
+          const int off = (16 * (WI0 + r) + lr) * kRowBytes + rd;
+          ah[r] = *reinterpret_cast<const lds_bf16x8*>(Ah + off);
+          if constexpr (G::TWO) al[r] = *reinterpret_cast<const lds_bf16x8*>(Ah + G::APL + off);
         }
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          const int off = (16 * (WJ0 + c) + lr) * kRowBytes + lg * 16;
-          const bf16x8 bh = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(Bh + off);
+          const int off = (16 * (WJ0 + c) + lr) * kRowBytes + rd;
+          const bf16x8 bh = *reinterpret_cast<const lds_bf16x8*>(Bh + off);
           bf16x8 bl;
-          if constexpr (G::TWO) bl = *reinterpret_cast<const __attribute__((address_space(3))) bf16x8*>(Bh + G::BPL + off);
+          if constexpr (G::TWO) bl = *reinterpret_cast<const lds_bf16x8*>(Bh + G::BPL + off);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
             acc[r][c] = mfma16<PREC>(ah[r], bh, acc[r][c]);
@@ -243,44 +198,124 @@ __device__ __forceinline__ void wave_loop(const PatchArgs& a, lds_t* smem, int b
           }
         }
       }
-
-      // ---- K-b: phase factors of the next chunk into the other buffer
-      generate(cur ^ 1, fn, ccn);
       __syncthreads();
     }
+    // second level: fold this run into the LDS tile
 #pragma unroll
     for (int r = 0; r < M; ++r)
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        tot[r][c] += acc[r][c];
+        my_tot[(r * N + c) * 64] = my_tot[(r * N + c) * 64] + acc[r][c];
         acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
   }
 
-  // ---- partial tile of this k-slice (rows/cols beyond the patch are padding)
+  // partial tile of this k-slice (rows/cols beyond the patch are padding)
 #pragma unroll
   for (int r = 0; r < M; ++r)
 #pragma unroll
     for (int c = 0; c < N; ++c) {
+      const f32x4 v = my_tot[(r * N + c) * 64];
       const int col = 16 * (WJ0 + c) + lr;  // tile-local
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = 16 * (WI0 + r) + 4 * lg + e;  // tile-local row
-        out[static_cast<size_t>(row) * width + col] = tot[r][c][e];
-      }
+      for (int e = 0; e < 4; ++e) out[static_cast<size_t>(16 * (WI0 + r) + 4 * lg + e) * width + col] = v[e];
     }
+}
+
+// Generator waves: waves 4 and 5 write A (tile rows), waves 6 and 7 write B
+// (tile columns).  Thread (visibility gv, class rc) of an axis writes rows
+// rc, rc + 8, rc + 16, ... of that axis for every chunk: one seed at row rc
+// and one step of 8 rows, both FP64-reduced.
+template <int PREC, int TBI, int TBJ, bool IS_A>
+__device__ __forceinline__ void gen_wave(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
+                                         int64_t ke, int64_t nch) {
+  using G = TileGeom<PREC, TBI, TBJ>;
+  constexpr int R = IS_A ? G::RA : G::RB;
+  const int pt = threadIdx.x - (IS_A ? 256 : 384);
+  const int gv = pt & 15, rc = pt >> 4;  // rc in 0..7
+  const double pos0 = IS_A ? (a.l_first + (16 * bi0 + rc) * a.dl) - a.l0 : (a.m_first + (16 * bj0 + rc) * a.dm) - a.m0;
+  const double d8 = 8.0 * (IS_A ? a.dl : a.dm);
+  constexpr int gstride = IS_A ? G::GA : G::GB;
+  constexpr int goff = IS_A ? 0 : G::NPL * G::APL;
+  constexpr int glo = IS_A ? G::APL : G::BPL;
+
+  // Branch-free fetch (a conditional load would make the compiler wait for
+  // it at once): past the end of the slice the last bin is read and its
+  // weight is zeroed when used.  B needs no zeroing, A's zero weight already
+  // cancels those terms.
+  const double* uv_axis = reinterpret_cast<const double*>(a.uvp) + (IS_A ? 0 : 1);
+  auto fetch = [&](int64_t n, double& f, cf32& cc, bool& ok) {
+    const int64_t kg = kb + n * kChunk + gv;
+    ok = kg < ke;
+    const int64_t kc = ok ? kg : ke - 1;
+    f = uv_axis[2 * kc];
+    if (IS_A) {
+      const float2 c = a.c[kc];
+      cc = {c.x, c.y};
+    }
+  };
+  auto generate = [&](int buf, double f, cf32 cc, bool ok) {
+    cf32 z = expi_turns(f * pos0);
+    cf32 zs = expi_turns(f * d8);
+    if (IS_A) {
+      if (!ok) cc = {0.f, 0.f};
+      z = conj(cmul(cc, z));
+      zs = conj(zs);
+    }
+    lds_t* plane = smem + buf * G::BUF + goff;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      store_operand<PREC>(plane, glo, gstride, rc + 8 * q, gv, z);
+      z = cmul(z, zs);
+    }
+  };
+
+  // Records are fetched kPrefetch chunks ahead into a register ring (slot =
+  // chunk mod kPrefetch), which hides the latency of the global loads.
+  constexpr int P = kPrefetch;
+  double ring_f[P];
+  cf32 ring_c[P];
+  bool ring_ok[P];
+  if (nch > 0) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) fetch(j, ring_f[j], ring_c[j], ring_ok[j]);
+    generate(0, ring_f[0], ring_c[0], ring_ok[0]);
+    fetch(P, ring_f[0], ring_c[0], ring_ok[0]);
+  }
+  __syncthreads();
+  // Chunk n+1 is generated while the contraction waves consume chunk n.  The
+  // last iteration writes a chunk past the end (zero weights) into the idle
+  // buffer; nothing reads it.
+  for (int64_t n = 0; n < nch; n += P) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (n + j >= nch) break;
+      const int slot = (j + 1) % P;  // holds chunk n + j + 1 (n is a multiple of P)
+      generate(static_cast<int>((n + j + 1) & 1), ring_f[slot], ring_c[slot], ring_ok[slot]);
+      fetch(n + j + 1 + P, ring_f[slot], ring_c[slot], ring_ok[slot]);
+      __syncthreads();
+    }
+  }
 }
 
 template <int PREC, int TBI, int TBJ>
 __device__ __forceinline__ void tile_body(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
                                           int64_t ke, float* out, int width) {
-  constexpr int M0 = (TBI + 1) / 2, M1 = TBI / 2, N0 = (TBJ + 1) / 2, N1 = TBJ / 2;
+  using G = TileGeom<PREC, TBI, TBJ>;
+  constexpr int M0 = G::M0, M1 = G::M1, N0 = G::N0, N1 = G::N1;
+  const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
+  lds_t* tot = smem + 2 * G::BUF;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   switch (wave) {
-    case 0: wave_loop<PREC, TBI, TBJ, M0, N0, 0, 0>(a, smem, bi0, bj0, kb, ke, out, width); break;
-    case 1: wave_loop<PREC, TBI, TBJ, M0, N1, 0, N0>(a, smem, bi0, bj0, kb, ke, out, width); break;
-    case 2: wave_loop<PREC, TBI, TBJ, M1, N0, M0, 0>(a, smem, bi0, bj0, kb, ke, out, width); break;
-    default: wave_loop<PREC, TBI, TBJ, M1, N1, M0, N0>(a, smem, bi0, bj0, kb, ke, out, width); break;
+    case 0: mfma_wave<PREC, TBI, TBJ, M0, N0, 0, 0>(a, smem, tot, nch, out, width); break;
+    case 1: mfma_wave<PREC, TBI, TBJ, M0, N1, 0, N0>(a, smem, tot + M0 * N0 * 1024, nch, out, width); break;
+    case 2: mfma_wave<PREC, TBI, TBJ, M1, N0, M0, 0>(a, smem, tot + M0 * (N0 + N1) * 1024, nch, out, width); break;
+    case 3:
+      mfma_wave<PREC, TBI, TBJ, M1, N1, M0, N0>(a, smem, tot + (M0 * (N0 + N1) + M1 * N0) * 1024, nch, out, width);
+      break;
+    case 4:
+    case 5: gen_wave<PREC, TBI, TBJ, true>(a, smem, bi0, bj0, kb, ke, nch); break;
+    default: gen_wave<PREC, TBI, TBJ, false>(a, smem, bi0, bj0, kb, ke, nch); break;
   }
 }
 
@@ -314,7 +349,7 @@ size_t tile_plan_partial_elems(const TilePlan& t) {
 // The contraction kernel.  Template arguments are the two tile heights and
 // the two tile widths (in blocks) of its tile family.
 template <int PREC, int I0, int I1, int J0, int J1>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
 void k_patch(PatchArgs a) {
   constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
   constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
@@ -432,13 +467,13 @@ template <int PREC>
 static hipError_t launch_family(const PatchArgs& a, dim3 grid, hipStream_t stream) {
   const TilePlan& t = a.tp;
   if (t.tbi[0] == 9 && t.tbi[1] == 8)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 9, 8>), grid, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 9, 8>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 9)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 5)
-    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(512), 0, stream, a);
   else
-    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(512), 0, stream, a);
   return hipGetLastError();
 }
 
