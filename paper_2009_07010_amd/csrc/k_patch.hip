@@ -11,8 +11,8 @@
 // k-slice, keeps the tile in matrix-core accumulators, and writes a partial
 // tile; K-f adds the partials in slice order (deterministic).
 //
-// A workgroup has 8 waves: 4 contraction waves and 4 generator waves, one
-// of each per SIMD, so the matrix core (contraction) and the vector ALU
+// A workgroup has 12 waves: 8 contraction waves and 4 generator waves, two
+// and one per SIMD, so the matrix core (contraction) and the vector ALU
 // (phase factors) of a SIMD work at the same time.  Per chunk of 16
 // visibilities
 //   * the generator waves write the next chunk's A and B columns for the
@@ -26,14 +26,15 @@
 // then FP32 complex multiplication along the rows.
 //
 // Tile and wave shapes are compile-time: a tile of TBI x TBJ 16x16 blocks is
-// cut into a 2 x 2 grid of contraction-wave sub-tiles whose block counts
-// differ by at most one; each wave runs the loop instantiated for its own
-// shape (chosen by a uniform switch on the wave index), so the contraction
-// is straight-line code with no per-block conditions.
+// cut into a 2 x 4 grid of contraction-wave sub-tiles whose block counts
+// differ by at most one per side; each wave runs the loop instantiated for
+// its own shape (chosen by a uniform switch on the wave index), so the
+// contraction is straight-line code with no per-block conditions.
 //
 // Two-level accumulation: matrix-core accumulators collect a run of
-// flush_chunks chunks and are then added into a second FP32 tile kept in
-// LDS.  A single FP32 accumulator over a whole k-slice loses up to ~2e-5 of
+// flush_chunks chunks and are then added into a second FP32 tile, the
+// workgroup's own partial slab in global memory (read-modify-write, no
+// atomics; it stays cache-resident).  A single FP32 accumulator over a whole k-slice loses up to ~2e-5 of
 // the peak at pixels where many nearly equal terms add up (the rounding of a
 // long sum of similar increments is coherent); short runs keep each
 // rounding small relative to the final value.
@@ -49,6 +50,7 @@ namespace psf {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 // LDS byte pointer (address space 3), so that every operand access is a
 // ds_read / ds_write with a 32-bit address rather than a flat access.
 typedef __attribute__((address_space(3))) uint8_t lds_t;
@@ -95,6 +97,8 @@ __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int g
     *reinterpret_cast<lds_f32*>(base + swz(row, slot + 1)) = z.im;
   } else {
     lds_t* p = hi_plane + row * kRowBytes + swz(row, v >> 2) + (v & 3) * 4;
+    // lo = v - hi, exact in FP32 (hi widened back: a shift or a mask for
+    // BF16, a conversion for FP16)
     uint32_t hi, lo = 0;
     if constexpr (PREC == kSplitFP16) {
       hi = pack_f16x2(z.re, z.im);
@@ -108,8 +112,7 @@ __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int g
   }
 }
 
-// LDS geometry of one tile type: two operand buffers and the second-level
-// accumulator tile of the four contraction waves.
+// LDS geometry of one tile type: two operand buffers.
 template <int PREC, int TBI, int TBJ>
 struct TileGeom {
   static constexpr int TI = 16 * TBI, TJ = 16 * TBJ;
@@ -120,34 +123,73 @@ struct TileGeom {
   static constexpr int APL = (F32 ? 2 : 1) * GA, BPL = (F32 ? 2 : 1) * GB;
   static constexpr int NPL = TWO ? 2 : 1;
   static constexpr int BUF = NPL * (APL + BPL);
-  static constexpr int TOT = TBI * TBJ * 1024;  // per 16x16 block: 64 lanes x 4 floats
-  static constexpr int LDS = 2 * BUF + TOT;
-  // wave sub-tiles: rows M0 then M1 blocks, columns N0 then N1
-  static constexpr int M0 = (TBI + 1) / 2, M1 = TBI / 2, N0 = (TBJ + 1) / 2, N1 = TBJ / 2;
+  static constexpr int LDS = 2 * BUF;
 };
 
-// Contraction wave: sub-tile of M x N blocks at block (WI0, WJ0) of the
-// tile; its second-level accumulators live in LDS at tot (block-major, in
-// accumulator lane order).
-template <int PREC, int TBI, int TBJ, int M, int N, int WI0, int WJ0>
-__device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, lds_t* tot, int64_t nch,
-                                          float* __restrict__ out, int width) {
+// Sub-tile of one contraction wave: m x n blocks at block (i0, j0) of the
+// tile; bit (r n + c) of `mask` set where block (i0 + r, j0 + c) belongs to
+// the wave.  Waves w and w + 4 share SIMD w mod 4.
+struct WaveShape {
+  int m, n, i0, j0;
+  uint64_t mask;
+};
+__host__ __device__ constexpr uint64_t full_mask(int m, int n) { return m * n == 64 ? ~0ULL : (1ULL << (m * n)) - 1; }
+
+__host__ __device__ constexpr WaveShape wave_shape(int TBI, int TBJ, int w) {
+  if (TBI == 9 && TBJ == 17) {
+    // 153 blocks, at most 20 per wave: four 5x4 sub-tiles over rows 0-4 and
+    // columns 0-15, three 4x5 over rows 5-8 and columns 0-14, and the rest
+    // (column 16, and column 15 of rows 5-8) as a 9x2 sub-tile with its
+    // top-left 5x1 strip masked out.
+    if (w < 4) return {5, 4, 0, 4 * w, full_mask(5, 4)};
+    if (w < 7) return {4, 5, 5, 5 * (w - 4), full_mask(4, 5)};
+    uint64_t m = full_mask(9, 2);
+    for (int r = 0; r < 5; ++r) m &= ~(1ULL << (2 * r));
+    return {9, 2, 0, 15, m};
+  }
+  // 2 block-row groups x 4 block-column groups whose sizes differ by at most
+  // one; the second row group takes the column groups shifted by one, so
+  // every SIMD gets one larger and one smaller sub-tile.
+  const int m0 = (TBI + 1) / 2;
+  const int q = w < 4 ? w : (w - 3) % 4;
+  const int j0 = (TBJ * q) / 4, n = (TBJ * (q + 1)) / 4 - j0;
+  return w < 4 ? WaveShape{m0, n, 0, j0, full_mask(m0, n)}
+               : WaveShape{TBI - m0, n, m0, j0, full_mask(TBI - m0, n)};
+}
+
+// Contraction wave W of a TBI x TBJ tile.  Its second-level accumulators
+// are its blocks of the workgroup's partial slab in global memory, laid out
+// [block][lane][4] in accumulator lane order (block = tile row block * TBJ +
+// tile column block).
+template <int PREC, int TBI, int TBJ, int W>
+__device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, int64_t nch, float* __restrict__ slab) {
   using G = TileGeom<PREC, TBI, TBJ>;
+  constexpr WaveShape S = wave_shape(TBI, TBJ, W);
+  constexpr int M = S.m, N = S.n, WI0 = S.i0, WJ0 = S.j0;
+  constexpr auto on = [](int r, int c) { return ((S.mask >> (r * N + c)) & 1) != 0; };
   typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
   typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
   const int rd = swz(lr, lg);  // swizzled chunk of this lane's operand reads (row = 16 b + lr)
-  lds_f32x4* my_tot = reinterpret_cast<lds_f32x4*>(tot) + lane;
+  // The slab is reached through a buffer resource: the lane offset is the
+  // only per-lane address register and each block's offset is a scalar, so
+  // no 64-bit block addresses are held across the contraction loop.
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(slab, 0, 256 * TBI * TBJ * static_cast<int>(sizeof(float)), 0x00020000);
+  const int voff = lane * 16;
+  auto slab_ld = [&](int blk) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, blk * 1024, 0));
+  };
+  auto slab_st = [&](int blk, f32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, blk * 1024, 0);
+  };
 
   f32x4 acc[M][N];
 #pragma unroll
   for (int r = 0; r < M; ++r)
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-      my_tot[(r * N + c) * 64] = acc[r][c];
-    }
+    for (int c = 0; c < N; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   __syncthreads();  // chunk 0 generated
 
   const int64_t flush = a.flush_chunks;
@@ -169,61 +211,87 @@ __device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, lds_t
                 *reinterpret_cast<const lds_f32x4*>(Bh + g * G::GB + (16 * (WJ0 + c) + lr) * kRowBytes + rd);
 #pragma unroll
             for (int r = 0; r < M; ++r)
+              if (on(r, c))
 #pragma unroll
-              for (int e = 0; e < 4; ++e)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], bv[e], acc[r][c], 0, 0, 0);
+                for (int e = 0; e < 4; ++e)
+                  acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], bv[e], acc[r][c], 0, 0, 0);
           }
         }
       } else {
-        bf16x8 ah[M], al[M];
+        // pass 1: A_hi x (B_hi, B_lo), keeping every B_hi fragment;
+        // pass 2: A_lo x B_hi.  Operand registers: 4 (M + N + 1).
+        // Loads run one column (pass 1) or one row (pass 2) ahead of their
+        // MFMAs; scheduling barriers keep the compiler from hoisting more
+        // loads than that, which would not fit the register budget.
+        auto ldA = [&](int plane, int r) {
+          return *reinterpret_cast<const lds_bf16x8*>(Ah + plane * G::APL + (16 * (WI0 + r) + lr) * kRowBytes + rd);
+        };
+        auto ldB = [&](int plane, int c) {
+          return *reinterpret_cast<const lds_bf16x8*>(Bh + plane * G::BPL + (16 * (WJ0 + c) + lr) * kRowBytes + rd);
+        };
+        bf16x8 ah[M], bh[N];
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-          const int off = (16 * (WI0 + r) + lr) * kRowBytes + rd;
-          ah[r] = *reinterpret_cast<const lds_bf16x8*>(Ah + off);
-          if constexpr (G::TWO) al[r] = *reinterpret_cast<const lds_bf16x8*>(Ah + G::APL + off);
-        }
+        for (int r = 0; r < M; ++r) ah[r] = ldA(0, r);
+        bf16x8 nbh = ldB(0, 0), nbl = {};
+        if constexpr (G::TWO) nbl = ldB(1, 0);
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          const int off = (16 * (WJ0 + c) + lr) * kRowBytes + rd;
-          const bf16x8 bh = *reinterpret_cast<const lds_bf16x8*>(Bh + off);
-          bf16x8 bl;
-          if constexpr (G::TWO) bl = *reinterpret_cast<const lds_bf16x8*>(Bh + G::BPL + off);
+          bh[c] = nbh;
+          const bf16x8 bl = nbl;
+          if (c + 1 < N) {
+            nbh = ldB(0, c + 1);
+            if constexpr (G::TWO) nbl = ldB(1, c + 1);
+          }
 #pragma unroll
           for (int r = 0; r < M; ++r) {
-            acc[r][c] = mfma16<PREC>(ah[r], bh, acc[r][c]);
-            if constexpr (G::TWO) {
-              acc[r][c] = mfma16<PREC>(ah[r], bl, acc[r][c]);
-              acc[r][c] = mfma16<PREC>(al[r], bh, acc[r][c]);
-            }
+            if (!on(r, c)) continue;
+            acc[r][c] = mfma16<PREC>(ah[r], bh[c], acc[r][c]);
+            if constexpr (G::TWO) acc[r][c] = mfma16<PREC>(ah[r], bl, acc[r][c]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (G::TWO) {
+          bf16x8 nal = ldA(1, 0);
+#pragma unroll
+          for (int r = 0; r < M; ++r) {
+            const bf16x8 al = nal;
+            if (r + 1 < M) nal = ldA(1, r + 1);
+#pragma unroll
+            for (int c = 0; c < N; ++c)
+              if (on(r, c)) acc[r][c] = mfma16<PREC>(al, bh[c], acc[r][c]);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
       __syncthreads();
     }
-    // second level: fold this run into the LDS tile
+    // second level: fold this run into the slab (the first run initialises
+    // it), one block row at a time so that the loaded partials do not all
+    // need registers at once
+    const bool first = run0 == 0;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        if (!on(r, c)) continue;
+        const int blk = (WI0 + r) * TBJ + (WJ0 + c);
+        slab_st(blk, first ? acc[r][c] : slab_ld(blk) + acc[r][c]);
+        acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (nch == 0) {
 #pragma unroll
     for (int r = 0; r < M; ++r)
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        my_tot[(r * N + c) * 64] = my_tot[(r * N + c) * 64] + acc[r][c];
-        acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
+      for (int c = 0; c < N; ++c)
+        if (on(r, c)) slab_st((WI0 + r) * TBJ + (WJ0 + c), acc[r][c]);
   }
-
-  // partial tile of this k-slice (rows/cols beyond the patch are padding)
-#pragma unroll
-  for (int r = 0; r < M; ++r)
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const f32x4 v = my_tot[(r * N + c) * 64];
-      const int col = 16 * (WJ0 + c) + lr;  // tile-local
-#pragma unroll
-      for (int e = 0; e < 4; ++e) out[static_cast<size_t>(16 * (WI0 + r) + 4 * lg + e) * width + col] = v[e];
-    }
 }
 
-// Generator waves: waves 4 and 5 write A (tile rows), waves 6 and 7 write B
-// (tile columns).  Thread (visibility gv, class rc) of an axis writes rows
+// Generator waves: waves 8 and 9 write A (tile rows), waves 10 and 11 write
+// B (tile columns).  Thread (visibility gv, class rc) of an axis writes rows
 // rc, rc + 8, rc + 16, ... of that axis for every chunk: one seed at row rc
 // and one step of 8 rows, both FP64-reduced.
 template <int PREC, int TBI, int TBJ, bool IS_A>
@@ -231,7 +299,7 @@ __device__ __forceinline__ void gen_wave(const PatchArgs& a, lds_t* smem, int bi
                                          int64_t ke, int64_t nch) {
   using G = TileGeom<PREC, TBI, TBJ>;
   constexpr int R = IS_A ? G::RA : G::RB;
-  const int pt = threadIdx.x - (IS_A ? 256 : 384);
+  const int pt = threadIdx.x - (IS_A ? 512 : 640);
   const int gv = pt & 15, rc = pt >> 4;  // rc in 0..7
   const double pos0 = IS_A ? (a.l_first + (16 * bi0 + rc) * a.dl) - a.l0 : (a.m_first + (16 * bj0 + rc) * a.dm) - a.m0;
   const double d8 = 8.0 * (IS_A ? a.dl : a.dm);
@@ -298,23 +366,48 @@ __device__ __forceinline__ void gen_wave(const PatchArgs& a, lds_t* smem, int bi
   }
 }
 
+// True if the eight contraction-wave sub-tiles cover every block of the tile
+// exactly once and no sub-tile holds more than 20 blocks (80 accumulator
+// registers).
+template <int TBI, int TBJ>
+constexpr bool wave_shapes_ok() {
+  int cover[TBI * TBJ] = {};
+  for (int w = 0; w < 8; ++w) {
+    const WaveShape s = wave_shape(TBI, TBJ, w);
+    if (s.m * s.n > 64 || s.i0 + s.m > TBI || s.j0 + s.n > TBJ) return false;
+    int nb = 0;
+    for (int r = 0; r < s.m; ++r)
+      for (int c = 0; c < s.n; ++c)
+        if ((s.mask >> (r * s.n + c)) & 1) {
+          ++cover[(s.i0 + r) * TBJ + s.j0 + c];
+          ++nb;
+        }
+    if (nb > 20) return false;
+  }
+  for (int b = 0; b < TBI * TBJ; ++b)
+    if (cover[b] != 1) return false;
+  return true;
+}
+
 template <int PREC, int TBI, int TBJ>
 __device__ __forceinline__ void tile_body(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
-                                          int64_t ke, float* out, int width) {
-  using G = TileGeom<PREC, TBI, TBJ>;
-  constexpr int M0 = G::M0, M1 = G::M1, N0 = G::N0, N1 = G::N1;
+                                          int64_t ke, float* slab) {
+  static_assert(wave_shapes_ok<TBI, TBJ>(), "contraction waves must cover the tile once");
   const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
-  lds_t* tot = smem + 2 * G::BUF;
+  // Waves 0-7 contract (sub-tiles from wave_shape); 8, 9 generate A and
+  // 10, 11 generate B, one generator wave per SIMD.
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   switch (wave) {
-    case 0: mfma_wave<PREC, TBI, TBJ, M0, N0, 0, 0>(a, smem, tot, nch, out, width); break;
-    case 1: mfma_wave<PREC, TBI, TBJ, M0, N1, 0, N0>(a, smem, tot + M0 * N0 * 1024, nch, out, width); break;
-    case 2: mfma_wave<PREC, TBI, TBJ, M1, N0, M0, 0>(a, smem, tot + M0 * (N0 + N1) * 1024, nch, out, width); break;
-    case 3:
-      mfma_wave<PREC, TBI, TBJ, M1, N1, M0, N0>(a, smem, tot + (M0 * (N0 + N1) + M1 * N0) * 1024, nch, out, width);
-      break;
-    case 4:
-    case 5: gen_wave<PREC, TBI, TBJ, true>(a, smem, bi0, bj0, kb, ke, nch); break;
+    case 0: mfma_wave<PREC, TBI, TBJ, 0>(a, smem, nch, slab); break;
+    case 1: mfma_wave<PREC, TBI, TBJ, 1>(a, smem, nch, slab); break;
+    case 2: mfma_wave<PREC, TBI, TBJ, 2>(a, smem, nch, slab); break;
+    case 3: mfma_wave<PREC, TBI, TBJ, 3>(a, smem, nch, slab); break;
+    case 4: mfma_wave<PREC, TBI, TBJ, 4>(a, smem, nch, slab); break;
+    case 5: mfma_wave<PREC, TBI, TBJ, 5>(a, smem, nch, slab); break;
+    case 6: mfma_wave<PREC, TBI, TBJ, 6>(a, smem, nch, slab); break;
+    case 7: mfma_wave<PREC, TBI, TBJ, 7>(a, smem, nch, slab); break;
+    case 8:
+    case 9: gen_wave<PREC, TBI, TBJ, true>(a, smem, bi0, bj0, kb, ke, nch); break;
     default: gen_wave<PREC, TBI, TBJ, false>(a, smem, bi0, bj0, kb, ke, nch); break;
   }
 }
@@ -339,6 +432,19 @@ __host__ __device__ inline int64_t tile_first_elem(const TilePlan& t, int ti, in
          cb * t.ns[r][1] * slab_elems(t, r, 1);
 }
 
+int tile_max_simd_blocks(int tbi, int tbj) {
+  int mx = 0;
+  for (int q = 0; q < 4; ++q) {
+    int nb = 0;
+    for (int w = q; w < 8; w += 4) {
+      const WaveShape s = wave_shape(tbi, tbj, w);
+      nb += __builtin_popcountll(s.mask);
+    }
+    mx = nb > mx ? nb : mx;
+  }
+  return mx;
+}
+
 int64_t tile_plan_workgroups(const TilePlan& t) {
   return t.ti_a * row_wgs(t, 0) + t.ti_b * row_wgs(t, 1);
 }
@@ -349,7 +455,7 @@ size_t tile_plan_partial_elems(const TilePlan& t) {
 // The contraction kernel.  Template arguments are the two tile heights and
 // the two tile widths (in blocks) of its tile family.
 template <int PREC, int I0, int I1, int J0, int J1>
-__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
+__global__ __attribute__((amdgpu_flat_work_group_size(768, 768), amdgpu_waves_per_eu(3, 3)))
 void k_patch(PatchArgs a) {
   constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
   constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
@@ -391,12 +497,12 @@ void k_patch(PatchArgs a) {
   const int64_t kps = t.kps[r][c];
   const int64_t kb = static_cast<int64_t>(split) * kps;
   const int64_t ke = min(a.K, kb + kps);
-  float* out = a.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(split) * slab_elems(t, r, c);
+  float* slab = a.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(split) * slab_elems(t, r, c);
   switch (r * 2 + c) {
-    case 0: tile_body<PREC, I0, J0>(a, smem, bi0, bj0, kb, ke, out, 16 * J0); break;
-    case 1: tile_body<PREC, I0, J1>(a, smem, bi0, bj0, kb, ke, out, 16 * J1); break;
-    case 2: tile_body<PREC, I1, J0>(a, smem, bi0, bj0, kb, ke, out, 16 * J0); break;
-    default: tile_body<PREC, I1, J1>(a, smem, bi0, bj0, kb, ke, out, 16 * J1); break;
+    case 0: tile_body<PREC, I0, J0>(a, smem, bi0, bj0, kb, ke, slab); break;
+    case 1: tile_body<PREC, I0, J1>(a, smem, bi0, bj0, kb, ke, slab); break;
+    case 2: tile_body<PREC, I1, J0>(a, smem, bi0, bj0, kb, ke, slab); break;
+    default: tile_body<PREC, I1, J1>(a, smem, bi0, bj0, kb, ke, slab); break;
   }
 }
 
@@ -408,12 +514,16 @@ __global__ __launch_bounds__(256) void k_finalize(PatchArgs a, float* __restrict
   const int i = static_cast<int>(idx / a.nm), j = static_cast<int>(idx - static_cast<int64_t>(i) * a.nm);
   const int span_i = t.ti_a * 16 * t.tbi[0], span_j = t.tj_a * 16 * t.tbj[0];
   const int r = i < span_i ? 0 : 1, c = j < span_j ? 0 : 1;
-  const int hi = 16 * t.tbi[r], wj = 16 * t.tbj[c];
+  const int hi = 16 * t.tbi[r], wj = 16 * t.tbj[c];  // tile height and width in pixels
   const int ti = r == 0 ? i / hi : t.ti_a + (i - span_i) / hi;
   const int tj = c == 0 ? j / wj : t.tj_a + (j - span_j) / wj;
   const int li = r == 0 ? i - ti * hi : i - span_i - (ti - t.ti_a) * hi;
   const int lj = c == 0 ? j - tj * wj : j - span_j - (tj - t.tj_a) * wj;
-  const float* p = a.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(li) * wj + lj;
+  // slab layout [block][lane][4]: block (li/16, lj/16), lane = col + 16 (row/4), element row % 4
+  const int blk = (li >> 4) * t.tbj[c] + (lj >> 4);
+  const int rr = li & 15, cc = lj & 15;
+  const float* p = a.partial + tile_first_elem(t, ti, tj) + (static_cast<int64_t>(blk) * 64 + cc + 16 * (rr >> 2)) * 4 +
+                   (rr & 3);
   const int64_t slab = slab_elems(t, r, c);
   float s = 0.f;
   for (int q = 0; q < t.ns[r][c]; ++q) s += p[q * slab];
@@ -421,15 +531,15 @@ __global__ __launch_bounds__(256) void k_finalize(PatchArgs a, float* __restrict
 }
 
 // ---------------------------------------------------------------- host side
-// Compiled tile families.  257-pixel patches (17 blocks a side): tiles of 9
-// then 8 blocks in each direction.  129: one 9x9 tile.  65: one 5x5 tile.
+// Compiled tile families.  257-pixel patches (17 blocks a side): full-width
+// tiles of 9 then 8 block rows.  129: one 9x9 tile.  65: one 5x5 tile.
 // Anything else: 8x8-block tiles over the padded patch.
 namespace {
 struct Family {
   int i0, i1, j0, j1;
 };
 Family family_for(int nbi, int nbj) {
-  if (nbi == 17 && nbj == 17) return {9, 8, 9, 8};
+  if (nbi == 17 && nbj == 17) return {9, 8, 17, 17};
   if (nbi == 9 && nbj == 9) return {9, 9, 9, 9};
   if (nbi == 5 && nbj == 5) return {5, 5, 5, 5};
   return {8, 8, 8, 8};
@@ -467,13 +577,13 @@ template <int PREC>
 static hipError_t launch_family(const PatchArgs& a, dim3 grid, hipStream_t stream) {
   const TilePlan& t = a.tp;
   if (t.tbi[0] == 9 && t.tbi[1] == 8)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 9, 8>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17>), grid, dim3(768), 0, stream, a);
   else if (t.tbi[0] == 9)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(768), 0, stream, a);
   else if (t.tbi[0] == 5)
-    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(768), 0, stream, a);
   else
-    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(768), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -107,18 +107,23 @@ ObsView view(const psf_obs* o) {
 // ------------------------------------------------------------------ planning
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int /*prec*/, int target_wgs) {
+PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
   PatchPlan p;
   TilePlan& t = p.tp;
   plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
   const int64_t chunks = std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk);
-  // k-slices per tile in proportion to the cost of one chunk of that tile
-  // (the block count of its largest wave), so that workgroups take alike
+  // k-slices per tile in proportion to the cost of one chunk of that tile,
+  // so that workgroups take alike: the larger of the matrix-core time of its
+  // largest contraction wave and the vector time of its busiest generator
+  // (cycles per 16-visibility chunk, as measured on MI355X)
   const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
+  const double mfma_per_block = prec == PSF_FP32 ? 256.0 : prec == PSF_PLAIN_BF16 ? 16.0 : 48.0;
   double cost[2][2], work = 0.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
-      cost[r][c] = ((t.tbi[r] + 1) / 2) * ((t.tbj[c] + 1) / 2);
+      const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c]);
+      const double gen = 4.7 * (8.0 * 2.0 * std::max(t.tbi[r], t.tbj[c]) + 60.0);
+      cost[r][c] = std::max(mf, gen);
       work += static_cast<double>(cnt_i[r]) * cnt_j[c] * cost[r][c];
     }
   for (int r = 0; r < 2; ++r)

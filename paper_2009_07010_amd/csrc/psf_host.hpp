@@ -12,9 +12,9 @@ namespace psf {
 // Workgroups one contraction launch aims for: one per compute unit of an
 // MI355X (256 CUs), the contraction kernels running one workgroup per CU.
 constexpr int kTargetWorkgroups = 256;
-// First-level accumulation run of the contraction: 32 chunks of 16
-// visibilities (512 terms per pixel) before folding into the second level.
-constexpr int kFlushChunks = 32;
+// First-level accumulation run of the contraction: 128 chunks of 16
+// visibilities (2048 terms per pixel) before folding into the second level.
+constexpr int kFlushChunks = 128;
 
 struct PatchPlan {
   TilePlan tp;

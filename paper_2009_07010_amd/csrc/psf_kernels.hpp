@@ -58,6 +58,8 @@ hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D
 // fills tbi, tbj and the tile counts of *tp (not ns / kps).
 void plan_tiles(int nbi, int nbj, TilePlan* tp);
 int64_t tile_plan_workgroups(const TilePlan& tp);
+// Blocks of the busiest SIMD (its two contraction waves) of a tbi x tbj tile.
+int tile_max_simd_blocks(int tbi, int tbj);
 size_t tile_plan_partial_elems(const TilePlan& tp);
 hipError_t launch_patch(int prec, const PatchArgs& a, hipStream_t stream);
 hipError_t launch_finalize(const PatchArgs& a, float* P, hipStream_t stream);
