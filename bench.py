@@ -98,11 +98,8 @@ def cpu_baseline(obs, src, n_bl_sub):
     import oracle as orc
     import psf_synth as ps
     B = min(n_bl_sub, obs.n_bl)
-    k1, tb1 = int(obs.bl_koff[B]), int(obs.bl_tboff[B])
-    sub = ps.Observation(ant_enu=obs.ant_enu, bl_ant=obs.bl_ant[:B], times_s=obs.times_s,
-                         uvw_m=obs.uvw_m[:B], freq_hz=obs.freq_hz, bl_bin=obs.bl_bin[:B],
-                         bl_koff=obs.bl_koff[:B + 1], bl_tboff=obs.bl_tboff[:B + 1],
-                         uvw_c_m=obs.uvw_c_m[:tb1], W=obs.W[:k1], name="sample")
+    k1 = int(obs.bl_koff[B])
+    sub = ps.first_baselines(obs, B)
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])

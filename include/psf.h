@@ -132,10 +132,18 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                       float* P_all, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of the patch with respect to the source direction, grid fixed:
- * given G_all = dLoss/dP (same layout as P_all), writes
- * grad_lm[s][0] = dLoss/dl0, grad_lm[s][1] = dLoss/dm0 (double, [n_src][2])
- * through D_k, the w-shift and the pixel offsets.  prec selects the
- * contraction arithmetic (PSF_FP32 or a split form). */
+ * given G_all = dLoss/dP (device, float, each source's [nl][nm] block at
+ * its out_off), writes grad_lm[s][0] = dLoss/dl0, grad_lm[s][1] =
+ * dLoss/dm0 (device, double, [n_src][2]).  The derivative of the patch
+ * definition [section 2.3, distorted-PSF equation] runs through D_k (its
+ * derivative over the bin's samples [section 2.3 averaging]), the
+ * linearised w-shift u'(l0, m0), v'(l0, m0) and the pixel offsets
+ * x_i = l_i - l0, y_j = m_j - m0.  Per source it forms five derivative
+ * patches with the forward contraction (arithmetic chosen by prec) and
+ * reduces them against G in FP64 in a fixed order (deterministic).
+ * h_srcs (host) gives directions, grids and out_off; d_srcs is not read
+ * (may be NULL).  G_all must hold every source's block: the library cannot
+ * check device extents. */
 int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                        const psf_src* d_srcs, const float* G_all, int prec,
                        double* grad_lm, void* ws, size_t ws_bytes, void* stream);

@@ -240,3 +240,84 @@ def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, wor
         D_ptr = Dr.data_ptr()
     psf_patch(dobs.struct, hs, D_ptr, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return P
+
+
+def patch_backward(dobs: DeviceObservation, srcs: Sequence, G_all, prec="split_bf16",
+                   workspace: Optional[Workspace] = None):
+    """dLoss/d(l0, m0) [n_src, 2] float64 on the device, from G_all = dLoss/dP
+    (float32, each source's [nl, nm] block concatenated in order)."""
+    torch = _torch()
+    arr = src_array(srcs)
+    need = psf_workspace_bytes(dobs.struct, arr, prec)
+    ws = (workspace or Workspace(dobs.device)).get(need)
+    total = sum(int(s.nl) * int(s.nm) for s in srcs)
+    G = G_all.to(device=dobs.device, dtype=torch.float32).contiguous()
+    if G.numel() != total:
+        raise ValueError(f"G_all has {G.numel()} elements, the patches {total}")
+    grad = torch.empty((len(srcs), 2), dtype=torch.float64, device=dobs.device)
+    psf_patch_backward(dobs.struct, arr, None, G.data_ptr(), prec, grad.data_ptr(), ws.data_ptr(), ws.numel(),
+                       _stream_handle())
+    return grad
+
+
+class _Grid:
+    """A source grid with its direction replaced."""
+
+    def __init__(self, g, l0: float, m0: float):
+        self.l0, self.m0 = l0, m0
+        self.l_first, self.m_first, self.dl, self.dm = g.l_first, g.m_first, g.dl, g.dm
+        self.nl, self.nm = g.nl, g.nm
+
+
+def _psf_patch_fn():
+    torch = _torch()
+
+    class PsfPatchFn(torch.autograd.Function):
+        """flux_s * P_s(l0_s, m0_s) for every source, [n_src, nl, nm] float32.
+
+        ``lm0`` float64 [n_src, 2] (any device; read on the host), ``flux``
+        [n_src]; ``grids`` gives each source's fixed pixel grid (l_first,
+        m_first, dl, dm, nl, nm, all patches the same size).  The backward
+        returns dLoss/d(lm0) from the library's adjoint (``psf_patch_backward``)
+        and dLoss/d(flux) = sum(grad_out * P_s).
+        """
+
+        @staticmethod
+        def forward(ctx, lm0, flux, dobs, grids, prec="split_bf16", workspace=None):
+            shapes = {(int(g.nl), int(g.nm)) for g in grids}
+            if len(shapes) != 1 or lm0.shape != (len(grids), 2) or flux.shape != (len(grids),):
+                raise ValueError("need lm0 [n_src, 2], flux [n_src] and equal patch sizes")
+            nl, nm = shapes.pop()
+            lm = lm0.detach().to("cpu", torch.float64)
+            srcs = [_Grid(g, float(lm[s, 0]), float(lm[s, 1])) for s, g in enumerate(grids)]
+            ws = workspace or Workspace(dobs.device)
+            P = torch.empty((len(srcs), nl, nm), dtype=torch.float32, device=dobs.device)
+            for s, src in enumerate(srcs):
+                patch(dobs, src, prec=prec, out=P[s], workspace=ws)
+            f = flux.detach().to(device=dobs.device, dtype=torch.float32)
+            ctx.save_for_backward(P, f)
+            ctx.srcs, ctx.dobs, ctx.prec, ctx.ws = srcs, dobs, prec, ws
+            ctx.lm_device, ctx.flux_device, ctx.flux_dtype = lm0.device, flux.device, flux.dtype
+            return f[:, None, None] * P
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            P, f = ctx.saved_tensors
+            grad_flux = (grad_out.double() * P.double()).sum(dim=(1, 2))
+            grad_flux = grad_flux.to(device=ctx.flux_device, dtype=ctx.flux_dtype)
+            G = (grad_out.double() * f.double()[:, None, None]).to(torch.float32).reshape(-1)
+            grad_lm = patch_backward(ctx.dobs, ctx.srcs, G, ctx.prec, ctx.ws).to(ctx.lm_device)
+            return grad_lm, grad_flux, None, None, None, None
+
+    return PsfPatchFn
+
+
+_PSF_PATCH_FN = None
+
+
+def psf_patch_fn():
+    """The torch.autograd.Function over the forward patch and its adjoint."""
+    global _PSF_PATCH_FN
+    if _PSF_PATCH_FN is None:
+        _PSF_PATCH_FN = _psf_patch_fn()
+    return _PSF_PATCH_FN

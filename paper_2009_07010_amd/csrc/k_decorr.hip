@@ -15,21 +15,36 @@
 // Derivatives for the adjoint: d phi/d l0 = du - dw l0/n0, d phi/d m0 =
 // dv - dw m0/n0 (du = (u_t nu_c - u_k nu_k)/c etc.), so
 // dD/dl0 = mean(-2 pi i dphi/dl0 exp(-2 pi i phi)).
+//
+// With c_k = W_k D_k, a_ki = exp(2 pi i u'_k x_i), b_kj = exp(2 pi i v'_k
+// y_j) and the pixel grid fixed (x_i = l_i - l0, y_j = m_j - m0):
+//   dP_ij/dl0 = 2 Re sum_k a_ki b_kj [W_k dD_k/dl0
+//               + 2 pi i c_k (du'_k/dl0 x_i + dv'_k/dl0 y_j - u'_k)]
+// and likewise for m0 (with -v'_k), where
+//   du'/dl0 = -w (1 - m0^2)/n0^3, du'/dm0 = dv'/dl0 = -w l0 m0/n0^3,
+//   dv'/dm0 = -w (1 - l0^2)/n0^3.
+// So every derivative patch is a sum of patches of the same form as P with
+// c_k replaced by one of five coefficient vectors, weighted by 1, x_i or y_j:
+//   e0 = W dD/dl0 - 2 pi i c u'    (weight 1, for l0)
+//   e1 = W dD/dm0 - 2 pi i c v'    (weight 1, for m0)
+//   e2 = 2 pi i c du'/dl0          (weight x_i, for l0)
+//   e3 = 2 pi i c dv'/dl0          (weight y_j for l0; weight x_i for m0)
+//   e4 = 2 pi i c dv'/dm0          (weight y_j, for m0)
 #include "psf_device.hpp"
 #include "psf_kernels.hpp"
 
 namespace psf {
 
 // One thread per bin.  Writes any subset of: D, record (u', v', c = W D),
-// and the two derivatives.  When D_in is given the samples are not read:
-// only the record is formed from the caller's D.
+// and the five adjoint coefficient vectors e0..e4 (coef_out, plane e at
+// coef_out + e K).  When D_in is given the samples are not read: only the
+// record is formed from the caller's D (no coefficients then).
 __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
                                                 const float2* __restrict__ D_in,
                                                 float2* __restrict__ D_out,
                                                 double2* __restrict__ uvp_out,
                                                 float2* __restrict__ c_out,
-                                                float2* __restrict__ dDl_out,
-                                                float2* __restrict__ dDm_out) {
+                                                float2* __restrict__ coef_out) {
   // No fused multiply-add in this kernel: the two products of the phase
   // difference must round alike so that identical rows cancel exactly.
 #pragma clang fp contract(off)
@@ -42,12 +57,13 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   const double uc = o.uvw_c[3 * r.tb + 0], vc = o.uvw_c[3 * r.tb + 1], wc = o.uvw_c[3 * r.tb + 2];
 
   float dre = 0.f, dim = 0.f;
+  float dDl_re = 0.f, dDl_im = 0.f, dDm_re = 0.f, dDm_im = 0.f;
+  const bool grad = coef_out != nullptr && D_in == nullptr;
   if (D_in != nullptr) {
     const float2 d = D_in[k];
     dre = d.x;
     dim = d.y;
   } else {
-    const bool grad = dDl_out != nullptr;
     const double A_k = uc * l0 + vc * m0 + wc * Lw;
     const double A_knu = A_k * nu_k;
     float sre = 0.f, sim = 0.f;
@@ -79,29 +95,47 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
     dim = sim * inv_n;
     if (grad) {
       const float s = 6.283185307179586f * inv_n;
-      dDl_out[k] = make_float2(glr * s, gli * s);
-      dDm_out[k] = make_float2(gmr * s, gmi * s);
+      dDl_re = glr * s;
+      dDl_im = gli * s;
+      dDm_re = gmr * s;
+      dDm_im = gmi * s;
     }
   }
   if (D_out != nullptr) D_out[k] = make_float2(dre, dim);
-  if (uvp_out != nullptr) {
-    const double s = nu_k * kInvCLight;
-    const double u = uc * s, v = vc * s, w = wc * s;
-    uvp_out[k] = make_double2(u - w * l0 / n0, v - w * m0 / n0);
-  }
-  if (c_out != nullptr) {
-    const float W = o.W[k];
-    c_out[k] = make_float2(W * dre, W * dim);
+  const double s = nu_k * kInvCLight;
+  const double u = uc * s, v = vc * s, w = wc * s;
+  const double up = u - w * l0 / n0, vp = v - w * m0 / n0;
+  if (uvp_out != nullptr) uvp_out[k] = make_double2(up, vp);
+  const float W = o.W[k];
+  const float cre = W * dre, cim = W * dim;
+  if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
+  if (grad) {
+    // 2 pi i c t = 2 pi t (-Im c, Re c) for real t.  All five vectors are
+    // scaled by kAdjointScale (a power of two, exact) so that they stay in
+    // the FP16 range of the split-FP16 contraction (|2 pi u' c| reaches a
+    // few 1e5 on km baselines at GHz); the reduction undoes the scale.
+    const double n03 = n0 * n0 * n0;
+    const double two_pi = 6.283185307179586 * kAdjointScale;
+    const float tu = static_cast<float>(two_pi * up), tv = static_cast<float>(two_pi * vp);
+    const float t2 = static_cast<float>(-two_pi * w * (1.0 - m0 * m0) / n03);
+    const float t3 = static_cast<float>(-two_pi * w * l0 * m0 / n03);
+    const float t4 = static_cast<float>(-two_pi * w * (1.0 - l0 * l0) / n03);
+    const int64_t K = o.K;
+    const float Ws = W * static_cast<float>(kAdjointScale);
+    coef_out[k] = make_float2(Ws * dDl_re - tu * -cim, Ws * dDl_im - tu * cre);
+    coef_out[K + k] = make_float2(Ws * dDm_re - tv * -cim, Ws * dDm_im - tv * cre);
+    coef_out[2 * K + k] = make_float2(t2 * -cim, t2 * cre);
+    coef_out[3 * K + k] = make_float2(t3 * -cim, t3 * cre);
+    coef_out[4 * K + k] = make_float2(t4 * -cim, t4 * cre);
   }
 }
 
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
-                         double2* uvp_out, float2* c_out, float2* dDl_out, float2* dDm_out,
-                         hipStream_t stream) {
+                         double2* uvp_out, float2* c_out, float2* coef_out, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
   hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0,
-                     m0, D_in, D_out, uvp_out, c_out, dDl_out, dDm_out);
+                     m0, D_in, D_out, uvp_out, c_out, coef_out);
   return hipGetLastError();
 }
 

@@ -145,6 +145,34 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
   return b;
 }
 
+// ------------------------------------------------------------------ contraction
+int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
+             const float2* c, float* partial, float* P, hipStream_t s) {
+  PatchArgs a;
+  a.uvp = uvp;
+  a.c = c;
+  a.K = obs->K;
+  a.l_first = h_src->l_first;
+  a.dl = h_src->dl;
+  a.l0 = h_src->l0;
+  a.m_first = h_src->m_first;
+  a.dm = h_src->dm;
+  a.m0 = h_src->m0;
+  a.nl = h_src->nl;
+  a.nm = h_src->nm;
+  a.tp = plan.tp;
+  a.flush_chunks = kFlushChunks;
+  a.partial = partial;
+  hipEvent_t ev0;
+  hipError_t e;
+  if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
+  e = launch_patch(prec, a, s);
+  if (e != hipSuccess) return hip_fail(e, "k_patch launch");
+  if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
+  e = launch_finalize(a, P, s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
+}
+
 // ------------------------------------------------------------------ timing
 namespace {
 struct Timing {
@@ -258,7 +286,7 @@ int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream)
   if ((st = check_device()) != PSF_OK) return st;
   if (obs->K == 0) return PSF_OK;
   hipError_t e = launch_decorr(view(obs), l0, m0, nullptr, reinterpret_cast<float2*>(D), nullptr, nullptr,
-                               nullptr, nullptr, static_cast<hipStream_t>(stream));
+                               nullptr, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_decorr launch");
 }
 
@@ -287,31 +315,10 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
   hipError_t e = hipSuccess;
   if (obs->K > 0) {
     e = launch_decorr(view(obs), h_src->l0, h_src->m0, reinterpret_cast<const float2*>(D), nullptr, uvp, c,
-                      nullptr, nullptr, s);
+                      nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
   }
-  PatchArgs a;
-  a.uvp = uvp;
-  a.c = c;
-  a.K = obs->K;
-  a.l_first = h_src->l_first;
-  a.dl = h_src->dl;
-  a.l0 = h_src->l0;
-  a.m_first = h_src->m_first;
-  a.dm = h_src->dm;
-  a.m0 = h_src->m0;
-  a.nl = h_src->nl;
-  a.nm = h_src->nm;
-  a.tp = plan.tp;
-  a.flush_chunks = kFlushChunks;
-  a.partial = partial;
-  hipEvent_t ev0;
-  if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_patch(prec, a, s);
-  if (e != hipSuccess) return hip_fail(e, "k_patch launch");
-  if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_finalize(a, P, s);
-  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
+  return contract(obs, h_src, plan, prec, uvp, c, partial, P, s);
 }
 
 }  // extern "C"

@@ -1,0 +1,133 @@
+// Adjoint of the patch with respect to the source direction (grid fixed).
+//
+// With G = dLoss/dP and the five coefficient vectors e0..e4 that k_decorr
+// forms per bin (derivation in k_decorr.hip), write Q[e] for the patch of
+// the same form as P with c_k replaced by e_k.  Then
+//   dLoss/dl0 = sum_ij G_ij (Q0 + x_i Q2 + y_j Q3)_ij
+//   dLoss/dm0 = sum_ij G_ij (Q1 + x_i Q3 + y_j Q4)_ij
+// Each Q[e] runs through the same phase-factor generation and matrix-core
+// contraction as the forward patch; k_grad_reduce forms the two sums in
+// FP64 with a fixed reduction order.  The e vectors arrive scaled by
+// kAdjointScale, which the reduction divides out.
+#include <algorithm>
+
+#include "psf_host.hpp"
+
+namespace psf {
+
+constexpr int kReduceThreads = 1024;
+
+__global__ __launch_bounds__(kReduceThreads) void k_grad_reduce(const float* __restrict__ G,
+                                                                const float* __restrict__ Pe, int nl, int nm,
+                                                                double l_first, double dl, double l0,
+                                                                double m_first, double dm, double m0,
+                                                                double* __restrict__ grad) {
+  const int64_t n = static_cast<int64_t>(nl) * nm;
+  double gl = 0.0, gm = 0.0;
+  for (int64_t p = threadIdx.x; p < n; p += kReduceThreads) {
+    const int i = static_cast<int>(p / nm), j = static_cast<int>(p - static_cast<int64_t>(i) * nm);
+    const double x = (l_first + i * dl) - l0, y = (m_first + j * dm) - m0;
+    const double g = G[p];
+    const double q0 = Pe[p], q1 = Pe[n + p], q2 = Pe[2 * n + p], q3 = Pe[3 * n + p], q4 = Pe[4 * n + p];
+    gl += g * (q0 + x * q2 + y * q3);
+    gm += g * (q1 + x * q3 + y * q4);
+  }
+  // fixed-order tree: butterfly within each wave, then across waves in LDS
+  for (int o = 32; o > 0; o >>= 1) {
+    gl += __shfl_xor(gl, o);
+    gm += __shfl_xor(gm, o);
+  }
+  __shared__ double part[2][kReduceThreads / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    part[0][wave] = gl;
+    part[1][wave] = gm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sl = 0.0, sm = 0.0;
+    for (int w = 0; w < kReduceThreads / 64; ++w) {
+      sl += part[0][w];
+      sm += part[1][w];
+    }
+    grad[0] = sl / kAdjointScale;
+    grad[1] = sm / kAdjointScale;
+  }
+}
+
+hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, double l_first, double dl,
+                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream) {
+  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(kReduceThreads), 0, stream, G, Pe, nl, nm, l_first, dl, l0,
+                     m_first, dm, m0, grad);
+  return hipGetLastError();
+}
+
+namespace {
+struct BackwardLayout {
+  size_t uvp, coef, partial, pe, total;
+};
+
+BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
+  size_t partial = 0, pix = 0;
+  for (int s = 0; s < n_src; ++s) {
+    partial = std::max(partial, plan_patch(o, &h_srcs[s], prec, kTargetWorkgroups).partial_elems);
+    pix = std::max(pix, static_cast<size_t>(h_srcs[s].nl) * h_srcs[s].nm);
+  }
+  BackwardLayout L;
+  const size_t K = static_cast<size_t>(o->K);
+  L.uvp = 0;
+  L.coef = L.uvp + align_up(K * sizeof(double2), 256);
+  L.partial = L.coef + align_up(5 * K * sizeof(float2), 256);
+  L.pe = L.partial + align_up(partial * sizeof(float), 256);
+  L.total = L.pe + align_up(5 * pix * sizeof(float), 256);
+  return L;
+}
+}  // namespace
+
+size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
+  return backward_layout(o, n_src, h_srcs, prec).total;
+}
+
+}  // namespace psf
+
+using namespace psf;
+
+extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, const psf_src* d_srcs,
+                                  const float* G_all, int prec, double* grad_lm, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  (void)d_srcs;
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if (n_src < 1 || h_srcs == nullptr) return fail(PSF_EINVAL, "need n_src >= 1 sources");
+  for (int s = 0; s < n_src; ++s)
+    if ((st = validate_src(&h_srcs[s], s)) != PSF_OK) return st;
+  if (G_all == nullptr || grad_lm == nullptr) return fail(PSF_EINVAL, "G_all or grad_lm is NULL");
+  const BackwardLayout L = backward_layout(obs, n_src, h_srcs, prec);
+  if (ws == nullptr || ws_bytes < L.total)
+    return fail(PSF_EWORKSPACE, "psf_patch_backward needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  double2* uvp = reinterpret_cast<double2*>(w + L.uvp);
+  float2* coef = reinterpret_cast<float2*>(w + L.coef);
+  float* partial = reinterpret_cast<float*>(w + L.partial);
+  float* pe = reinterpret_cast<float*>(w + L.pe);
+  const int64_t K = obs->K;
+  for (int n = 0; n < n_src; ++n) {
+    const psf_src& src = h_srcs[n];
+    const int64_t pix = static_cast<int64_t>(src.nl) * src.nm;
+    hipError_t e;
+    if (K > 0) {
+      e = launch_decorr(view(obs), src.l0, src.m0, nullptr, nullptr, uvp, nullptr, coef, s);
+      if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
+    }
+    const PatchPlan plan = plan_patch(obs, &src, prec, kTargetWorkgroups);
+    for (int q = 0; q < 5; ++q)
+      if ((st = contract(obs, &src, plan, prec, uvp, coef + q * K, partial, pe + q * pix, s)) != PSF_OK) return st;
+    e = launch_grad_reduce(G_all + src.out_off, pe, src.nl, src.nm, src.l_first, src.dl, src.l0, src.m_first,
+                           src.dm, src.m0, grad_lm + 2 * n, s);
+    if (e != hipSuccess) return hip_fail(e, "k_grad_reduce launch");
+  }
+  return PSF_OK;
+}

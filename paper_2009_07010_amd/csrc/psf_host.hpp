@@ -32,6 +32,11 @@ size_t align_up(size_t x, size_t a);
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs);
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 
+// The contraction and finalise of one patch from per-bin records (u', v')
+// and coefficients c (c_k = W_k D_k for the patch itself).
+int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
+             const float2* c, float* partial, float* P, hipStream_t s);
+
 size_t batched_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 

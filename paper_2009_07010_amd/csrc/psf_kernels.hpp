@@ -50,9 +50,19 @@ struct PatchArgs {
 
 constexpr int kPatchChunk = 16;  // visibilities per contraction chunk
 
+// Power-of-two scale of the adjoint coefficient vectors (keeps them inside
+// the FP16 range; exact in every precision).
+constexpr double kAdjointScale = 1.0 / 4096.0;
+
+// coef_out (optional, [5][K]): the adjoint coefficient vectors e0..e4 (see
+// k_decorr.hip) times kAdjointScale; needs D_in == nullptr.
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
-                         double2* uvp_out, float2* c_out, float2* dDl_out, float2* dDm_out,
-                         hipStream_t stream);
+                         double2* uvp_out, float2* c_out, float2* coef_out, hipStream_t stream);
+// dLoss/d(l0, m0) of one source from G = dLoss/dP and the five derivative
+// patches Pe [5][nl][nm] of the coefficient vectors e0..e4, FP64, written
+// to grad[0..1].
+hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, double l_first, double dl,
+                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream);
 
 // Tile shapes of the compiled contraction for a patch of nbi x nbj blocks;
 // fills tbi, tbj and the tile counts of *tp (not ns / kps).

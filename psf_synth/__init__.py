@@ -366,6 +366,17 @@ def perturbed_targets(config: int, srcs: Sequence[Source], seed: int = 0, sigma_
     return out
 
 
+def first_baselines(obs: Observation, n_bl: int) -> Observation:
+    """The same observation restricted to its first ``n_bl`` baselines (a
+    bounded sample of a large workload)."""
+    B = min(int(n_bl), obs.n_bl)
+    k1, tb1 = int(obs.bl_koff[B]), int(obs.bl_tboff[B])
+    return Observation(ant_enu=obs.ant_enu, bl_ant=obs.bl_ant[:B], times_s=obs.times_s,
+                       uvw_m=obs.uvw_m[:B], freq_hz=obs.freq_hz, bl_bin=obs.bl_bin[:B],
+                       bl_koff=obs.bl_koff[:B + 1], bl_tboff=obs.bl_tboff[:B + 1],
+                       uvw_c_m=obs.uvw_c_m[:tb1], W=obs.W[:k1], name=f"{obs.name}[:{B}]")
+
+
 # --------------------------------------------------------------------------
 # small random observations for property tests and edge cases
 # --------------------------------------------------------------------------

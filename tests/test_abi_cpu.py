@@ -103,10 +103,27 @@ def test_workspace_too_small(L):
     need = ctypes.c_size_t(0)
     assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, 1, ctypes.byref(need)) == 0
     assert need.value > 12 * 24
-    st, msg = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, FAKE, need.value - 1, None)
+    # the reported size covers every entry point; the records alone (24 B per
+    # bin) already exceed 12 * 24 - 1 bytes
+    st, msg = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, FAKE, 12 * 24 - 1, None)
     assert st == pk.PSF_EWORKSPACE and "workspace" in msg
     st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, None, need.value, None)
     assert st == pk.PSF_EWORKSPACE
+    grad = FAKE
+    st, msg = status_of(L.psf_patch_backward, ctypes.byref(o), 1, srcs, None, FAKE, 1, grad, FAKE,
+                        12 * 24 - 1, None)
+    assert st == pk.PSF_EWORKSPACE and "workspace" in msg
+
+
+def test_backward_argument_errors(L):
+    o, s = fake_obs(), fake_src()
+    srcs = (pk.PsfSrc * 1)(s)
+    st, _ = status_of(L.psf_patch_backward, ctypes.byref(o), 0, srcs, None, FAKE, 1, FAKE, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_patch_backward, ctypes.byref(o), 1, srcs, None, None, 1, FAKE, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_patch_backward, ctypes.byref(o), 1, srcs, None, FAKE, 9, FAKE, FAKE, 1 << 30, None)
+    assert st == pk.PSF_EINVAL
 
 
 def test_decorr_bad_direction(L):

@@ -1,0 +1,163 @@
+"""GPU parity of the adjoint (psf_patch_backward behind the autograd
+Function) against the FP64 oracle's analytic gradient and its central finite
+differences.
+
+The loss is the patch-fitting loss of the differentiation workload:
+L = sum_s || f_s P_s(l0_s, m0_s) - T_s ||^2 on fixed grids.  Gradient parity
+bar: 1e-4 relative, per source, to the largest of its two direction
+components (and 1e-4 relative for the flux component).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import psf_synth as ps
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden")
+GRAD_TOL = 1e-4
+PRECS = ["fp32", "split_bf16", "split_fp16"]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2009_07010_amd as pk
+    pk.lib()
+    return pk
+
+
+def _gpu_loss_grad(pk, obs, srcs, fluxes, targets, prec):
+    dobs = pk.DeviceObservation(obs)
+    fn = pk.psf_patch_fn()
+    lm = torch.tensor([[s.l0, s.m0] for s in srcs], dtype=torch.float64, requires_grad=True)
+    f = torch.tensor(fluxes, dtype=torch.float32, device="cuda", requires_grad=True)
+    T = torch.as_tensor(np.stack(targets), dtype=torch.float32, device="cuda")
+    out = fn.apply(lm, f, dobs, srcs, prec)
+    loss = ((out.double() - T.double()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), lm.grad.numpy().copy(), f.grad.double().cpu().numpy()
+
+
+def _check(g_lm, g_f, ref_lm, ref_f, label, flux_scale=None):
+    """Direction components relative to the larger of the source's two; the
+    flux component relative to itself, or to ``flux_scale[s]`` where given
+    (the sum of the magnitudes of the terms of dL/dflux = 2 sum r P, which
+    cancel near the optimum)."""
+    for s in range(len(ref_lm)):
+        scale = np.max(np.abs(ref_lm[s]))
+        err = np.max(np.abs(g_lm[s] - ref_lm[s])) / scale
+        fs = abs(ref_f[s]) if flux_scale is None else flux_scale[s]
+        ferr = abs(g_f[s] - ref_f[s]) / fs
+        print(f"{label} src{s}: dir rel err {err:.2e}  (|grad| {scale:.3e}); flux rel err {ferr:.2e} "
+              f"(plain {abs(g_f[s] - ref_f[s]) / abs(ref_f[s]):.2e})", flush=True)
+        assert err <= GRAD_TOL, (label, s, g_lm[s], ref_lm[s])
+        assert ferr <= GRAD_TOL, (label, s, g_f[s], ref_f[s])
+
+
+def _config1_case():
+    obs = ps.observation(1)
+    base = ps.sources(1)[0]
+    cell = 2.0 * ps.ARCSEC
+    dirs = [(base.l0, base.m0), (-0.4 * ps.DEG, 0.7 * ps.DEG), (1.1 * ps.DEG, -0.2 * ps.DEG)]
+    srcs = [ps.Source.centred(l0, m0, 65, cell) for l0, m0 in dirs]
+    fluxes = [1.0, 0.3, 0.05]
+    g = np.random.default_rng(7)
+    moved = [s.with_direction(s.l0 + g.normal(0, ps.ARCSEC), s.m0 + g.normal(0, ps.ARCSEC)) for s in srcs]
+    targets = [(f * orc.patch_factored(obs, m)).astype(np.float32) for f, m in zip(fluxes, moved)]
+    return obs, srcs, fluxes, targets
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_backward_config1_vs_oracle(pk, prec):
+    """K = 420 only: the split-BF16 patch carries close to its per-term error
+    bound here, and dL/dflux = 2 sum r P cancels, so the flux component is
+    measured against the magnitude of its terms."""
+    obs, srcs, fluxes, targets = _config1_case()
+    T64 = [t.astype(np.float64) for t in targets]
+    L_ref, g_ref, gf_ref = orc.loss_grad_analytic(obs, srcs, fluxes, T64)
+    P64 = [orc.patch_factored(obs, s) for s in srcs]
+    fscale = [2.0 * np.sum(np.abs((f * P - T) * P)) for f, P, T in zip(fluxes, P64, T64)]
+    L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, targets, prec)
+    assert abs(L - L_ref) <= 1e-3 * L_ref
+    _check(g_lm, g_f, g_ref, gf_ref, f"config1 {prec}", flux_scale=fscale)
+
+
+def test_backward_config1_vs_finite_differences(pk):
+    """Against central differences (h = 1e-3 arcsec) of the FP64 oracle loss."""
+    obs, srcs, fluxes, targets = _config1_case()
+    T64 = [t.astype(np.float64) for t in targets]
+    g_fd = orc.loss_grad_fd(obs, srcs, fluxes, T64)
+    _, g_ref, gf_ref = orc.loss_grad_analytic(obs, srcs, fluxes, T64)
+    _, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, targets, "split_bf16")
+    for s in range(len(srcs)):
+        scale = np.max(np.abs(g_fd[s]))
+        err = np.max(np.abs(g_lm[s] - g_fd[s])) / scale
+        print(f"config1 FD src{s}: rel err {err:.2e}", flush=True)
+        assert err <= GRAD_TOL
+
+
+def _golden_case(tag, obs):
+    meta = json.load(open(os.path.join(GOLD, tag + ".json")))
+    srcs = ps.sources(3, seed=0)[:meta["n_src"]]
+    T = np.load(os.path.join(GOLD, tag + "_targets.npy"))
+    ref = np.load(os.path.join(GOLD, tag + "_grad.npy"))
+    return srcs, [s.flux for s in srcs], list(T), ref, meta
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_backward_config3_first_64_baselines(pk, prec):
+    obs = ps.first_baselines(ps.observation(3, seed=0), 64)
+    srcs, fluxes, T, ref, meta = _golden_case("config3_seed0_bl64", obs)
+    assert obs.K == meta["K"]
+    L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, T, prec)
+    assert abs(L - meta["loss"]) <= 1e-3 * meta["loss"]
+    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3/64bl {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_backward_config3_full(pk, prec):
+    tag = "config3_seed0"
+    if not os.path.exists(os.path.join(GOLD, tag + "_grad.npy")):
+        pytest.skip("golden values for the full differentiation workload not generated")
+    obs = ps.observation(3, seed=0)
+    srcs, fluxes, T, ref, meta = _golden_case(tag, obs)
+    assert obs.K == meta["K"]
+    L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, T, prec)
+    assert abs(L - meta["loss"]) <= 1e-3 * meta["loss"]
+    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3 {prec}")
+
+
+def test_backward_zero_cotangent_and_repeatability(pk):
+    obs, srcs, fluxes, targets = _config1_case()
+    dobs = pk.DeviceObservation(obs)
+    n = sum(s.nl * s.nm for s in srcs)
+    zero = pk.patch_backward(dobs, srcs, torch.zeros(n, device="cuda"), "split_bf16")
+    assert torch.count_nonzero(zero).item() == 0
+    G = torch.as_tensor(np.random.default_rng(3).standard_normal(n), dtype=torch.float32, device="cuda")
+    a = pk.patch_backward(dobs, srcs, G, "split_bf16")
+    b = pk.patch_backward(dobs, srcs, G, "split_bf16")
+    assert torch.equal(a, b)
+
+
+def test_backward_linear_in_cotangent(pk):
+    """The adjoint is linear in G: grad(2 G1 - G2) = 2 grad(G1) - grad(G2)."""
+    obs, srcs, _, _ = _config1_case()
+    dobs = pk.DeviceObservation(obs)
+    n = sum(s.nl * s.nm for s in srcs)
+    g = np.random.default_rng(11)
+    G1 = torch.as_tensor(g.standard_normal(n), dtype=torch.float32, device="cuda")
+    G2 = torch.as_tensor(g.standard_normal(n), dtype=torch.float32, device="cuda")
+    a = pk.patch_backward(dobs, srcs, G1, "fp32")
+    b = pk.patch_backward(dobs, srcs, G2, "fp32")
+    c = pk.patch_backward(dobs, srcs, 2 * G1 - G2, "fp32")
+    scale = torch.max(torch.abs(a)) + torch.max(torch.abs(b))
+    assert torch.max(torch.abs(c - (2 * a - b))) <= 1e-5 * scale
