@@ -321,3 +321,60 @@ def psf_patch_fn():
     if _PSF_PATCH_FN is None:
         _PSF_PATCH_FN = _psf_patch_fn()
     return _PSF_PATCH_FN
+
+
+def device_sources(srcs: Sequence, device="cuda"):
+    """(host PsfSrc array, device copy of it as a uint8 tensor).  The device
+    copy is what the batched call reads directions and grids from at run
+    time; write new directions into it (``set_directions``) to replay a
+    captured graph for other sources."""
+    torch = _torch()
+    h = src_array(srcs)
+    raw = bytes(memoryview(h).cast("B"))
+    d = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+    return h, d
+
+
+def set_directions(d_srcs, lm0) -> None:
+    """Overwrite (l0, m0) of every source in a device source array with the
+    rows of ``lm0`` (float64 [n_src, 2], same device); grids stay."""
+    torch = _torch()
+    n = lm0.shape[0]
+    rec = ctypes.sizeof(PsfSrc) // 8
+    view = d_srcs.view(torch.float64).view(n, rec)
+    view[:, 0:2].copy_(lm0)
+
+
+def patch_batched(dobs: DeviceObservation, srcs: Sequence, prec="split_bf16", tuning: Optional[str] = None,
+                  out=None, workspace: Optional[Workspace] = None, d_srcs=None):
+    """Every source's patch in one call, concatenated float32 [sum nl*nm] in
+    source order (``split_patches`` cuts it).  ``d_srcs`` (from
+    ``device_sources``) may be passed to reuse a device source array."""
+    torch = _torch()
+    h, d = device_sources(srcs, dobs.device) if d_srcs is None else (src_array(srcs), d_srcs)
+    need = psf_workspace_bytes(dobs.struct, h, prec)
+    ws = (workspace or Workspace(dobs.device)).get(need)
+    total = sum(int(s.nl) * int(s.nm) for s in srcs)
+    P = torch.empty(total, dtype=torch.float32, device=dobs.device) if out is None else out
+    psf_patch_batched(dobs.struct, h, d.data_ptr(), prec, None if tuning is None else tuning.encode(),
+                      P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    return P
+
+
+def split_patches(P_all, srcs: Sequence):
+    """The per-source [nl, nm] views of a concatenated patch array."""
+    out, off = [], 0
+    for s in srcs:
+        n = int(s.nl) * int(s.nm)
+        out.append(P_all[off:off + n].view(int(s.nl), int(s.nm)))
+        off += n
+    return out
+
+
+def autotune(dobs: DeviceObservation, srcs: Sequence, prec="split_bf16", workspace: Optional[Workspace] = None) -> str:
+    """Times candidate launch shapes per tile family on these sources and
+    returns the JSON tuning table for ``patch_batched``."""
+    h = src_array(srcs)
+    need = psf_workspace_bytes(dobs.struct, h, prec)
+    ws = (workspace or Workspace(dobs.device)).get(need)
+    return psf_autotune(dobs.struct, h, prec, ws.data_ptr(), ws.numel(), _stream_handle())

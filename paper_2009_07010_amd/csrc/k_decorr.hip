@@ -39,7 +39,14 @@ namespace psf {
 // and the five adjoint coefficient vectors e0..e4 (coef_out, plane e at
 // coef_out + e K).  When D_in is given the samples are not read: only the
 // record is formed from the caller's D (no coefficients then).
+//
+// Several sources per launch: grid row y handles source y, whose direction
+// is read from device memory at dirs + y * dir_stride (l0, m0 as the first
+// two doubles) when dirs is given, and whose records start y * rec_stride
+// elements into uvp_out and c_out.
 __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
+                                                const double* __restrict__ dirs, int64_t dir_stride,
+                                                int64_t rec_stride,
                                                 const float2* __restrict__ D_in,
                                                 float2* __restrict__ D_out,
                                                 double2* __restrict__ uvp_out,
@@ -50,6 +57,12 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
 #pragma clang fp contract(off)
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= o.K) return;
+  if (dirs != nullptr) {
+    l0 = dirs[blockIdx.y * dir_stride];
+    m0 = dirs[blockIdx.y * dir_stride + 1];
+  }
+  if (uvp_out != nullptr) uvp_out += blockIdx.y * rec_stride;
+  if (c_out != nullptr) c_out += blockIdx.y * rec_stride;
   const BinRef r = locate_bin(o.koff, o.tboff, o.bl_bin, o.n_bl, o.n_t, o.n_ch, k);
   const double n0 = sqrt(1.0 - l0 * l0 - m0 * m0);
   const double Lw = n0 - 1.0;
@@ -135,7 +148,16 @@ hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
   hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0,
-                     m0, D_in, D_out, uvp_out, c_out, coef_out);
+                     m0, nullptr, int64_t(0), int64_t(0), D_in, D_out, uvp_out, c_out, coef_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t dir_stride, int n_src,
+                                 double2* uvp_out, float2* c_out, int64_t rec_stride, hipStream_t stream) {
+  const int threads = 256;
+  const int64_t blocks = (o.K + threads - 1) / threads;
+  hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(n_src)), dim3(threads), 0,
+                     stream, o, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, nullptr, uvp_out, c_out, nullptr);
   return hipGetLastError();
 }
 

@@ -69,6 +69,14 @@ constexpr int kPrefetch = 4;  // chunks of per-bin records held ahead by a gener
 
 __device__ __forceinline__ int swz(int row, int chunk) { return (chunk ^ ((row >> 1) & 3)) << 4; }
 
+// What the tile body needs of one work item's source.
+struct TileArgs {
+  const double2* uvp;
+  const float2* c;
+  double l_first, dl, l0, m_first, dm, m0;
+  int flush_chunks;
+};
+
 template <int PREC>
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, f32x4 acc) {
   if constexpr (PREC == kSplitFP16) {
@@ -157,12 +165,23 @@ __host__ __device__ constexpr WaveShape wave_shape(int TBI, int TBJ, int w) {
                : WaveShape{TBI - m0, n, m0, j0, full_mask(TBI - m0, n)};
 }
 
+// A 16-byte vector store reads its data registers after it issues; a VALU
+// write to those registers in the very next cycle can change what is stored
+// (seen as corrupted slab elements when the compiler placed a 64-bit move
+// into the stored registers right after the store).  One wait state after
+// each slab store closes that window.
+__device__ __forceinline__ void store_data_guard() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 1");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // Contraction wave W of a TBI x TBJ tile.  Its second-level accumulators
 // are its blocks of the workgroup's partial slab in global memory, laid out
 // [block][lane][4] in accumulator lane order (block = tile row block * TBJ +
 // tile column block).
 template <int PREC, int TBI, int TBJ, int W>
-__device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, int64_t nch, float* __restrict__ slab) {
+__device__ __forceinline__ void mfma_wave(const TileArgs& a, lds_t* smem, int64_t nch, float* __restrict__ slab) {
   using G = TileGeom<PREC, TBI, TBJ>;
   constexpr WaveShape S = wave_shape(TBI, TBJ, W);
   constexpr int M = S.m, N = S.n, WI0 = S.i0, WJ0 = S.j0;
@@ -183,6 +202,7 @@ __device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, int64
   };
   auto slab_st = [&](int blk, f32x4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), rs, voff, blk * 1024, 0);
+    store_data_guard();
   };
 
   f32x4 acc[M][N];
@@ -295,7 +315,7 @@ __device__ __forceinline__ void mfma_wave(const PatchArgs& a, lds_t* smem, int64
 // rc, rc + 8, rc + 16, ... of that axis for every chunk: one seed at row rc
 // and one step of 8 rows, both FP64-reduced.
 template <int PREC, int TBI, int TBJ, bool IS_A>
-__device__ __forceinline__ void gen_wave(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
+__device__ __forceinline__ void gen_wave(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
                                          int64_t ke, int64_t nch) {
   using G = TileGeom<PREC, TBI, TBJ>;
   constexpr int R = IS_A ? G::RA : G::RB;
@@ -389,42 +409,39 @@ constexpr bool wave_shapes_ok() {
   return true;
 }
 
-template <int PREC, int TBI, int TBJ>
-__device__ __forceinline__ void tile_body(const PatchArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
+// The work of one wave role on one work item.  Roles: 0-7 contraction
+// sub-tiles (wave_shape), 8 the A generator (waves 8, 9), 10 the B
+// generator (waves 10, 11); one generator wave per SIMD.
+template <int PREC, int TBI, int TBJ, int ROLE>
+__device__ __forceinline__ void role_body(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
                                           int64_t ke, float* slab) {
   static_assert(wave_shapes_ok<TBI, TBJ>(), "contraction waves must cover the tile once");
   const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
-  // Waves 0-7 contract (sub-tiles from wave_shape); 8, 9 generate A and
-  // 10, 11 generate B, one generator wave per SIMD.
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  switch (wave) {
-    case 0: mfma_wave<PREC, TBI, TBJ, 0>(a, smem, nch, slab); break;
-    case 1: mfma_wave<PREC, TBI, TBJ, 1>(a, smem, nch, slab); break;
-    case 2: mfma_wave<PREC, TBI, TBJ, 2>(a, smem, nch, slab); break;
-    case 3: mfma_wave<PREC, TBI, TBJ, 3>(a, smem, nch, slab); break;
-    case 4: mfma_wave<PREC, TBI, TBJ, 4>(a, smem, nch, slab); break;
-    case 5: mfma_wave<PREC, TBI, TBJ, 5>(a, smem, nch, slab); break;
-    case 6: mfma_wave<PREC, TBI, TBJ, 6>(a, smem, nch, slab); break;
-    case 7: mfma_wave<PREC, TBI, TBJ, 7>(a, smem, nch, slab); break;
-    case 8:
-    case 9: gen_wave<PREC, TBI, TBJ, true>(a, smem, bi0, bj0, kb, ke, nch); break;
-    default: gen_wave<PREC, TBI, TBJ, false>(a, smem, bi0, bj0, kb, ke, nch); break;
-  }
+  if constexpr (ROLE < 8)
+    mfma_wave<PREC, TBI, TBJ, ROLE>(a, smem, nch, slab);
+  else
+    gen_wave<PREC, TBI, TBJ, ROLE == 8>(a, smem, bi0, bj0, kb, ke, nch);
 }
 
 // ---------------------------------------------------------------- tile plan
-__host__ __device__ inline int64_t slab_elems(const TilePlan& t, int r, int c) {
+// Templates over the plan's type so that device code indexes a plan in the
+// kernel-argument segment in place (constant address space, scalar loads).
+template <class TP>
+__host__ __device__ inline int64_t slab_elems(const TP& t, int r, int c) {
   return 256LL * t.tbi[r] * t.tbj[c];
 }
-__host__ __device__ inline int64_t row_wgs(const TilePlan& t, int r) {
+template <class TP>
+__host__ __device__ inline int64_t row_wgs(const TP& t, int r) {
   return static_cast<int64_t>(t.tj_a) * t.ns[r][0] + static_cast<int64_t>(t.tj_b) * t.ns[r][1];
 }
-__host__ __device__ inline int64_t row_elems(const TilePlan& t, int r) {
+template <class TP>
+__host__ __device__ inline int64_t row_elems(const TP& t, int r) {
   return static_cast<int64_t>(t.tj_a) * t.ns[r][0] * slab_elems(t, r, 0) +
          static_cast<int64_t>(t.tj_b) * t.ns[r][1] * slab_elems(t, r, 1);
 }
 // Element offset of the first slab of tile (ti, tj).
-__host__ __device__ inline int64_t tile_first_elem(const TilePlan& t, int ti, int tj) {
+template <class TP>
+__host__ __device__ inline int64_t tile_first_elem(const TP& t, int ti, int tj) {
   const int r = ti < t.ti_a ? 0 : 1;
   const int ra = ti < t.ti_a ? ti : t.ti_a, rb = ti - ra;
   const int ca = tj < t.tj_a ? tj : t.tj_a, cb = tj - ca;
@@ -436,35 +453,37 @@ int tile_max_simd_blocks(int tbi, int tbj) {
   int mx = 0;
   for (int q = 0; q < 4; ++q) {
     int nb = 0;
-    for (int w = q; w < 8; w += 4) {
-      const WaveShape s = wave_shape(tbi, tbj, w);
-      nb += __builtin_popcountll(s.mask);
-    }
+    for (int w = q; w < 8; w += 4) nb += __builtin_popcountll(wave_shape(tbi, tbj, w).mask);
     mx = nb > mx ? nb : mx;
   }
   return mx;
 }
 
-int64_t tile_plan_workgroups(const TilePlan& t) {
+int64_t tile_plan_items(const TilePlan& t) {
   return t.ti_a * row_wgs(t, 0) + t.ti_b * row_wgs(t, 1);
 }
 size_t tile_plan_partial_elems(const TilePlan& t) {
   return static_cast<size_t>(t.ti_a * row_elems(t, 0) + t.ti_b * row_elems(t, 1));
 }
 
-// The contraction kernel.  Template arguments are the two tile heights and
-// the two tile widths (in blocks) of its tile family.
-template <int PREC, int I0, int I1, int J0, int J1>
-__global__ __attribute__((amdgpu_flat_work_group_size(768, 768), amdgpu_waves_per_eu(3, 3)))
-void k_patch(PatchArgs a) {
-  constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
-  constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
-  constexpr int LA = L00 > L01 ? L00 : L01, LB = L10 > L11 ? L10 : L11;
-  __shared__ __attribute__((aligned(16))) uint8_t smem_raw[LA > LB ? LA : LB];
-  lds_t* smem = (lds_t*)smem_raw;
-  const TilePlan& t = a.tp;
-  // decode (tile row, tile column, k-slice) from the workgroup index
-  int64_t w = blockIdx.x;
+typedef const __attribute__((address_space(4))) SrcPlan karg_plan;
+
+// One work item, decoded.
+struct Item {
+  int type;  // tile type: row type * 2 + column type
+  int bi0, bj0;
+  int64_t kb, ke;
+  float* slab;
+  TileArgs ta;
+};
+
+__device__ __forceinline__ Item decode_item(const BatchArgs& a, karg_plan* plans, int64_t item) {
+  int s = 0;
+  while (s + 1 < a.n_src && item >= plans[s + 1].item0) ++s;
+  karg_plan& p = plans[s];
+  const auto& t = p.tp;
+  // (tile row, tile column, k-slice) from the item index
+  int64_t w = item - p.item0;
   int r, ti;
   int64_t wr;
   const int64_t rwa = row_wgs(t, 0);
@@ -492,26 +511,95 @@ void k_patch(PatchArgs a) {
     tj = t.tj_a + q;
     split = static_cast<int>(wr - static_cast<int64_t>(q) * t.ns[r][1]);
   }
-  const int bi0 = ti < t.ti_a ? ti * t.tbi[0] : t.ti_a * t.tbi[0] + (ti - t.ti_a) * t.tbi[1];
-  const int bj0 = tj < t.tj_a ? tj * t.tbj[0] : t.tj_a * t.tbj[0] + (tj - t.tj_a) * t.tbj[1];
+  Item it;
+  it.type = r * 2 + c;
+  it.bi0 = ti < t.ti_a ? ti * t.tbi[0] : t.ti_a * t.tbi[0] + (ti - t.ti_a) * t.tbi[1];
+  it.bj0 = tj < t.tj_a ? tj * t.tbj[0] : t.tj_a * t.tbj[0] + (tj - t.tj_a) * t.tbj[1];
   const int64_t kps = t.kps[r][c];
-  const int64_t kb = static_cast<int64_t>(split) * kps;
-  const int64_t ke = min(a.K, kb + kps);
-  float* slab = a.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(split) * slab_elems(t, r, c);
-  switch (r * 2 + c) {
-    case 0: tile_body<PREC, I0, J0>(a, smem, bi0, bj0, kb, ke, slab); break;
-    case 1: tile_body<PREC, I0, J1>(a, smem, bi0, bj0, kb, ke, slab); break;
-    case 2: tile_body<PREC, I1, J0>(a, smem, bi0, bj0, kb, ke, slab); break;
-    default: tile_body<PREC, I1, J1>(a, smem, bi0, bj0, kb, ke, slab); break;
+  it.kb = static_cast<int64_t>(split) * kps;
+  it.ke = min(a.K, it.kb + kps);
+  it.slab = p.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(split) * slab_elems(t, r, c);
+  it.ta.uvp = p.uvp;
+  it.ta.c = p.c;
+  it.ta.flush_chunks = a.flush_chunks;
+  if (p.dir != nullptr) {
+    it.ta.l0 = p.dir[0];
+    it.ta.m0 = p.dir[1];
+    it.ta.l_first = p.dir[2];
+    it.ta.m_first = p.dir[3];
+    it.ta.dl = p.dir[4];
+    it.ta.dm = p.dir[5];
+  } else {
+    it.ta.l0 = p.l0;
+    it.ta.m0 = p.m0;
+    it.ta.l_first = p.l_first;
+    it.ta.m_first = p.m_first;
+    it.ta.dl = p.dl;
+    it.ta.dm = p.dm;
+  }
+  return it;
+}
+
+// The persistent item loop of one wave role.  Every wave of a workgroup
+// takes the same items, so the barriers inside the items match; the last
+// barrier of an item orders its LDS reads before the next item's first LDS
+// writes.  Each role has its own loop so that what the compiler keeps live
+// across items is only that role's.
+template <int PREC, int I0, int I1, int J0, int J1, int ROLE>
+__device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, lds_t* smem) {
+  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    const Item it = decode_item(a, plans, item);
+    switch (it.type) {
+      case 0: role_body<PREC, I0, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 1: role_body<PREC, I0, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 2: role_body<PREC, I1, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      default: role_body<PREC, I1, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+    }
+  }
+}
+
+// The contraction kernel: a persistent loop over the work items of the
+// launch's sources.  Template arguments are the two tile heights and the two
+// tile widths (in blocks) of its tile family.
+template <int PREC, int I0, int I1, int J0, int J1>
+__global__ __attribute__((amdgpu_flat_work_group_size(768, 768), amdgpu_waves_per_eu(3, 3)))
+void k_patch(BatchArgs a) {
+  constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
+  constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
+  constexpr int LA = L00 > L01 ? L00 : L01, LB = L10 > L11 ? L10 : L11;
+  __shared__ __attribute__((aligned(16))) uint8_t smem_raw[LA > LB ? LA : LB];
+  lds_t* smem = (lds_t*)smem_raw;
+  // The per-source plans are read straight from the kernel-argument segment
+  // (the argument starts at its offset 0): indexing the by-value parameter
+  // with a run-time index would copy it to private memory.
+  typedef const __attribute__((address_space(4))) uint8_t karg_byte;
+  karg_plan* plans = (karg_plan*)((karg_byte*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(BatchArgs, src));
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  switch (wave) {
+    case 0: role_loop<PREC, I0, I1, J0, J1, 0>(a, plans, smem); break;
+    case 1: role_loop<PREC, I0, I1, J0, J1, 1>(a, plans, smem); break;
+    case 2: role_loop<PREC, I0, I1, J0, J1, 2>(a, plans, smem); break;
+    case 3: role_loop<PREC, I0, I1, J0, J1, 3>(a, plans, smem); break;
+    case 4: role_loop<PREC, I0, I1, J0, J1, 4>(a, plans, smem); break;
+    case 5: role_loop<PREC, I0, I1, J0, J1, 5>(a, plans, smem); break;
+    case 6: role_loop<PREC, I0, I1, J0, J1, 6>(a, plans, smem); break;
+    case 7: role_loop<PREC, I0, I1, J0, J1, 7>(a, plans, smem); break;
+    case 8:
+    case 9: role_loop<PREC, I0, I1, J0, J1, 8>(a, plans, smem); break;
+    default: role_loop<PREC, I0, I1, J0, J1, 10>(a, plans, smem); break;
   }
 }
 
 // K-f: P = 2 * sum over the k-slices of the pixel's tile, in slice order.
-__global__ __launch_bounds__(256) void k_finalize(PatchArgs a, float* __restrict__ P) {
+// Grid row y is source y of the launch.
+__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
+  (void)a;
+  typedef const __attribute__((address_space(4))) uint8_t karg_byte;
+  karg_plan& p = ((karg_plan*)((karg_byte*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(BatchArgs, src)))[blockIdx.y];
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= static_cast<int64_t>(a.nl) * a.nm) return;
-  const TilePlan& t = a.tp;
-  const int i = static_cast<int>(idx / a.nm), j = static_cast<int>(idx - static_cast<int64_t>(i) * a.nm);
+  if (idx >= static_cast<int64_t>(p.nl) * p.nm) return;
+  const auto& t = p.tp;
+  const int i = static_cast<int>(idx / p.nm), j = static_cast<int>(idx - static_cast<int64_t>(i) * p.nm);
   const int span_i = t.ti_a * 16 * t.tbi[0], span_j = t.tj_a * 16 * t.tbj[0];
   const int r = i < span_i ? 0 : 1, c = j < span_j ? 0 : 1;
   const int hi = 16 * t.tbi[r], wj = 16 * t.tbj[c];  // tile height and width in pixels
@@ -522,12 +610,12 @@ __global__ __launch_bounds__(256) void k_finalize(PatchArgs a, float* __restrict
   // slab layout [block][lane][4]: block (li/16, lj/16), lane = col + 16 (row/4), element row % 4
   const int blk = (li >> 4) * t.tbj[c] + (lj >> 4);
   const int rr = li & 15, cc = lj & 15;
-  const float* p = a.partial + tile_first_elem(t, ti, tj) + (static_cast<int64_t>(blk) * 64 + cc + 16 * (rr >> 2)) * 4 +
+  const float* q = p.partial + tile_first_elem(t, ti, tj) + (static_cast<int64_t>(blk) * 64 + cc + 16 * (rr >> 2)) * 4 +
                    (rr & 3);
   const int64_t slab = slab_elems(t, r, c);
-  float s = 0.f;
-  for (int q = 0; q < t.ns[r][c]; ++q) s += p[q * slab];
-  P[idx] = 2.0f * s;
+  float sum = 0.f;
+  for (int n = 0; n < t.ns[r][c]; ++n) sum += q[n * slab];
+  p.P[idx] = 2.0f * sum;
 }
 
 // ---------------------------------------------------------------- host side
@@ -574,8 +662,8 @@ void plan_tiles(int nbi, int nbj, TilePlan* t) {
 }
 
 template <int PREC>
-static hipError_t launch_family(const PatchArgs& a, dim3 grid, hipStream_t stream) {
-  const TilePlan& t = a.tp;
+static hipError_t launch_family(const BatchArgs& a, dim3 grid, hipStream_t stream) {
+  const TilePlan& t = a.src[0].tp;
   if (t.tbi[0] == 9 && t.tbi[1] == 8)
     hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17>), grid, dim3(768), 0, stream, a);
   else if (t.tbi[0] == 9)
@@ -587,8 +675,13 @@ static hipError_t launch_family(const PatchArgs& a, dim3 grid, hipStream_t strea
   return hipGetLastError();
 }
 
-hipError_t launch_patch(int prec, const PatchArgs& a, hipStream_t stream) {
-  const dim3 grid(static_cast<unsigned>(tile_plan_workgroups(a.tp)));
+hipError_t launch_patch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t stream) {
+  if (a.n_src < 1 || a.n_src > kMaxBatch || n_wg < 1) return hipErrorInvalidValue;
+  for (int s = 1; s < a.n_src; ++s)  // one tile family per launch
+    if (a.src[s].tp.tbi[0] != a.src[0].tp.tbi[0] || a.src[s].tp.tbi[1] != a.src[0].tp.tbi[1] ||
+        a.src[s].tp.tbj[0] != a.src[0].tp.tbj[0] || a.src[s].tp.tbj[1] != a.src[0].tp.tbj[1])
+      return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(n_wg));
   switch (prec) {
     case kFP32: return launch_family<kFP32>(a, grid, stream);
     case kSplitBF16: return launch_family<kSplitBF16>(a, grid, stream);
@@ -598,11 +691,12 @@ hipError_t launch_patch(int prec, const PatchArgs& a, hipStream_t stream) {
   }
 }
 
-hipError_t launch_finalize(const PatchArgs& a, float* P, hipStream_t stream) {
-  const int64_t n = static_cast<int64_t>(a.nl) * a.nm;
+hipError_t launch_finalize(const BatchArgs& a, hipStream_t stream) {
+  int64_t n = 0;
+  for (int s = 0; s < a.n_src; ++s) n = max(n, static_cast<int64_t>(a.src[s].nl) * a.src[s].nm);
   const int threads = 256;
-  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>((n + threads - 1) / threads)), dim3(threads), 0,
-                     stream, a, P);
+  hipLaunchKernelGGL(k_finalize, dim3(static_cast<unsigned>((n + threads - 1) / threads), a.n_src),
+                     dim3(threads), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -107,34 +107,54 @@ ObsView view(const psf_obs* o) {
 // ------------------------------------------------------------------ planning
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
-  PatchPlan p;
-  TilePlan& t = p.tp;
-  plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
-  const int64_t chunks = std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk);
-  // k-slices per tile in proportion to the cost of one chunk of that tile,
-  // so that workgroups take alike: the larger of the matrix-core time of its
-  // largest contraction wave and the vector time of its busiest generator
-  // (cycles per 16-visibility chunk, as measured on MI355X)
-  const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
+// Cost of one 16-visibility chunk of each tile type of a tile plan, in SIMD
+// cycles as measured on MI355X: the larger of the matrix-core time of the
+// busiest SIMD's two contraction waves and the vector time of the busiest
+// generator wave.
+static void chunk_costs(const TilePlan& t, int prec, double cost[2][2]) {
   const double mfma_per_block = prec == PSF_FP32 ? 256.0 : prec == PSF_PLAIN_BF16 ? 16.0 : 48.0;
-  double cost[2][2], work = 0.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c]);
       const double gen = 4.7 * (8.0 * 2.0 * std::max(t.tbi[r], t.tbj[c]) + 60.0);
       cost[r][c] = std::max(mf, gen);
-      work += static_cast<double>(cnt_i[r]) * cnt_j[c] * cost[r][c];
     }
+}
+
+double patch_work(const psf_obs* o, const psf_src* s, int prec) {
+  TilePlan t;
+  plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
+  double cost[2][2];
+  chunk_costs(t, prec, cost);
+  const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
+  const double chunks = static_cast<double>(std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk));
+  double work = 0.0;
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) work += static_cast<double>(cnt_i[r]) * cnt_j[c] * cost[r][c] * chunks;
+  return work;
+}
+
+PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double item_work) {
+  PatchPlan p;
+  TilePlan& t = p.tp;
+  plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
+  const int64_t chunks = std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk);
+  double cost[2][2];
+  chunk_costs(t, prec, cost);
+  // k-slices per tile so that every work item costs about item_work
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
-      int64_t n = static_cast<int64_t>(std::llround(target_wgs * cost[r][c] / work));
+      int64_t n = static_cast<int64_t>(std::llround(cost[r][c] * static_cast<double>(chunks) / item_work));
       n = std::min<int64_t>(std::max<int64_t>(1, n), chunks);
       t.ns[r][c] = static_cast<int>(n);
       t.kps[r][c] = ((chunks + n - 1) / n) * kPatchChunk;
     }
   p.partial_elems = tile_plan_partial_elems(t);
   return p;
+}
+
+PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
+  return plan_patch_items(o, s, prec, patch_work(o, s, prec) / target_wgs);
 }
 
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
@@ -146,31 +166,47 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
 }
 
 // ------------------------------------------------------------------ contraction
-int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
-             const float2* c, float* partial, float* P, hipStream_t s) {
-  PatchArgs a;
-  a.uvp = uvp;
-  a.c = c;
-  a.K = obs->K;
-  a.l_first = h_src->l_first;
-  a.dl = h_src->dl;
-  a.l0 = h_src->l0;
-  a.m_first = h_src->m_first;
-  a.dm = h_src->dm;
-  a.m0 = h_src->m0;
-  a.nl = h_src->nl;
-  a.nm = h_src->nm;
-  a.tp = plan.tp;
-  a.flush_chunks = kFlushChunks;
-  a.partial = partial;
+SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const double2* uvp, const float2* c, float* partial,
+                 float* P, const double* dir) {
+  SrcPlan p;
+  p.tp = plan.tp;
+  p.item0 = 0;
+  p.uvp = uvp;
+  p.c = c;
+  p.partial = partial;
+  p.P = P;
+  p.dir = dir;
+  p.l0 = h_src->l0;
+  p.m0 = h_src->m0;
+  p.l_first = h_src->l_first;
+  p.m_first = h_src->m_first;
+  p.dl = h_src->dl;
+  p.dm = h_src->dm;
+  p.nl = h_src->nl;
+  p.nm = h_src->nm;
+  return p;
+}
+
+int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
   hipEvent_t ev0;
   hipError_t e;
   if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_patch(prec, a, s);
+  e = launch_patch(prec, a, n_wg, s);
   if (e != hipSuccess) return hip_fail(e, "k_patch launch");
   if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_finalize(a, P, s);
+  e = launch_finalize(a, s);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
+}
+
+int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
+             const float2* c, float* partial, float* P, hipStream_t s) {
+  BatchArgs a;
+  a.n_src = 1;
+  a.flush_chunks = kFlushChunks;
+  a.K = obs->K;
+  a.src[0] = src_plan(h_src, plan, uvp, c, partial, P, nullptr);
+  a.n_items = tile_plan_items(plan.tp);
+  return run_batch(prec, a, a.n_items, s);
 }
 
 // ------------------------------------------------------------------ timing

@@ -29,6 +29,11 @@ int validate_src(const psf_src* s, int idx);
 int validate_prec(int prec);
 ObsView view(const psf_obs* o);
 size_t align_up(size_t x, size_t a);
+// Matrix-core / generator cost of a source's whole patch (SIMD cycles).
+double patch_work(const psf_obs* o, const psf_src* s, int prec);
+// Tile plan whose work items each cost about item_work.
+PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double item_work);
+// Tile plan with about target_wgs work items.
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs);
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 
@@ -36,6 +41,11 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 // and coefficients c (c_k = W_k D_k for the patch itself).
 int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
              const float2* c, float* partial, float* P, hipStream_t s);
+
+SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const double2* uvp, const float2* c, float* partial,
+                 float* P, const double* dir);
+// Contraction (n_wg persistent workgroups) and finalise of the sources of a.
+int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s);
 
 size_t batched_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);

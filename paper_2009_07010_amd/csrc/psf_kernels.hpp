@@ -35,17 +35,33 @@ struct TilePlan {
   int64_t kps[2][2];
 };
 
-// One source's patch contraction over precomputed per-bin records.
-struct PatchArgs {
-  const double2* uvp;        // [K] (u'_k, v'_k) in wavelengths
-  const float2* c;           // [K] W_k D_k
-  int64_t K;
-  double l_first, dl, l0;
-  double m_first, dm, m0;
-  int nl, nm;                // patch size
+// Per-source part of a contraction launch.  A launch contracts the patches
+// of up to kMaxBatch sources of one tile family; its work items (tile,
+// k-slice) are numbered source by source (src[s].item0 is the first item of
+// source s) and tile by tile within a source as TilePlan describes.
+struct SrcPlan {
   TilePlan tp;
-  int flush_chunks;          // chunks per first-level (matrix-core) accumulation run
-  float* partial;            // partial slabs, see TilePlan
+  int64_t item0;
+  const double2* uvp;  // [K] (u'_k, v'_k) in wavelengths
+  const float2* c;     // [K] W_k D_k (or an adjoint coefficient vector)
+  float* partial;      // partial slabs, see TilePlan
+  float* P;            // output patch [nl][nm]
+  // Source direction and pixel grid: read at run time from `dir` (device
+  // memory laid out as psf_src: l0, m0, l_first, m_first, dl, dm) when it
+  // is not null, else taken from the fields below.
+  const double* dir;
+  double l0, m0, l_first, m_first, dl, dm;
+  int nl, nm;
+};
+
+constexpr int kMaxBatch = 16;
+
+struct BatchArgs {
+  int n_src;
+  int flush_chunks;  // chunks per first-level (matrix-core) accumulation run
+  int64_t K;
+  int64_t n_items;
+  SrcPlan src[kMaxBatch];
 };
 
 constexpr int kPatchChunk = 16;  // visibilities per contraction chunk
@@ -58,6 +74,11 @@ constexpr double kAdjointScale = 1.0 / 4096.0;
 // k_decorr.hip) times kAdjointScale; needs D_in == nullptr.
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
                          double2* uvp_out, float2* c_out, float2* coef_out, hipStream_t stream);
+// Records of n_src sources in one launch: source y's direction is read from
+// device memory (dirs + y dir_stride: l0, m0), its records are written at
+// uvp_out / c_out + y rec_stride.
+hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t dir_stride, int n_src,
+                                 double2* uvp_out, float2* c_out, int64_t rec_stride, hipStream_t stream);
 // dLoss/d(l0, m0) of one source from G = dLoss/dP and the five derivative
 // patches Pe [5][nl][nm] of the coefficient vectors e0..e4, FP64, written
 // to grad[0..1].
@@ -67,11 +88,15 @@ hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, d
 // Tile shapes of the compiled contraction for a patch of nbi x nbj blocks;
 // fills tbi, tbj and the tile counts of *tp (not ns / kps).
 void plan_tiles(int nbi, int nbj, TilePlan* tp);
-int64_t tile_plan_workgroups(const TilePlan& tp);
 // Blocks of the busiest SIMD (its two contraction waves) of a tbi x tbj tile.
 int tile_max_simd_blocks(int tbi, int tbj);
 size_t tile_plan_partial_elems(const TilePlan& tp);
-hipError_t launch_patch(int prec, const PatchArgs& a, hipStream_t stream);
-hipError_t launch_finalize(const PatchArgs& a, float* P, hipStream_t stream);
+// Work items of one source's tile plan.
+int64_t tile_plan_items(const TilePlan& tp);
+// Contraction of every item of `a` with `grid` persistent workgroups (each
+// takes items blockIdx.x, blockIdx.x + grid, ...).
+hipError_t launch_patch(int prec, const BatchArgs& a, int64_t grid, hipStream_t stream);
+// P = 2 * (sum of the k-slices) for every source of `a`.
+hipError_t launch_finalize(const BatchArgs& a, hipStream_t stream);
 
 }  // namespace psf

@@ -61,12 +61,79 @@ def _config3(obs, tag, n_src):
     print(tag, time.time() - t)
 
 
+def _config3_flux_scale(obs, tag):
+    """sum_ij |2 r_ij P_ij| per source (r = flux P - T): the magnitude of the
+    terms of dL/dflux, which cancel near the optimum; the scale the flux
+    derivative's error is measured against."""
+    meta = json.load(open(os.path.join(HERE, tag + ".json")))
+    srcs = ps.sources(3, seed=0)[:meta["n_src"]]
+    T = np.load(os.path.join(HERE, tag + "_targets.npy")).astype(np.float64)
+    out = []
+    for s, t in zip(srcs, T):
+        P = orc.patch_factored(obs, s)
+        out.append(2.0 * np.sum(np.abs((s.flux * P - t) * P)))
+    np.save(os.path.join(HERE, tag + "_fluxscale.npy"), np.array(out))
+    print(tag, "flux scale", out)
+
+
+def config3_sub_fluxscale():
+    _config3_flux_scale(ps.first_baselines(ps.observation(3, seed=0), 64), "config3_seed0_bl64")
+
+
+def config3_fluxscale():
+    _config3_flux_scale(ps.observation(3, seed=0), "config3_seed0")
+
+
 def config3_sub():
     _config3(ps.first_baselines(ps.observation(3, seed=0), 64), "config3_seed0_bl64", 4)
 
 
 def config3():
     _config3(ps.observation(3, seed=0), "config3_seed0", 4)
+
+
+def config5_pixels(srcs, n_side):
+    """Sampled pixels of a patch: the centre, the four corners, edge
+    midpoints and seeded random pixels (row, column indices)."""
+    out = []
+    for s in srcs:
+        nl, nm = s.nl, s.nm
+        fixed = [(nl // 2, nm // 2), (0, 0), (0, nm - 1), (nl - 1, 0), (nl - 1, nm - 1),
+                 (nl // 2, 0), (0, nm // 2), (nl - 1, nm // 2), (nl // 2, nm - 1)]
+        g = np.random.default_rng(5)
+        rnd = [(int(g.integers(nl)), int(g.integers(nm))) for _ in range(n_side - len(fixed))]
+        ij = np.array(fixed + rnd)
+        out.append(ij)
+    return out
+
+
+def config5_sources():
+    """One source of each patch size of workload 5: the first of each size."""
+    srcs = ps.sources(5, seed=0)
+    idx = []
+    for n in (65, 129, 257):
+        idx.append(next(i for i, s in enumerate(srcs) if s.nl == n))
+    return idx
+
+
+def config5():
+    obs = ps.observation(5, seed=0)
+    srcs = ps.sources(5, seed=0)
+    idx = config5_sources()
+    pix = config5_pixels([srcs[i] for i in idx], 24)
+    t = time.time()
+    rows = []
+    for i, ij in zip(idx, pix):
+        D = orc.decorr(obs, srcs[i].l0, srcs[i].m0)
+        P = orc.patch_pixels(obs, srcs[i], ij[:, 0], ij[:, 1], D)
+        peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+        for (a, b), v in zip(ij, P):
+            rows.append((i, a, b, v, peak))
+        print("config5 source", i, time.time() - t, flush=True)
+    np.save(os.path.join(HERE, "config5_seed0_pixels.npy"), np.array(rows, dtype=np.float64))
+    _meta("config5_seed0", config=5, seed=0, K=obs.K, sources=idx, seconds=time.time() - t,
+          what="oracle.patch_pixels (FP64) at sampled pixels of one source per patch size of workload 5; "
+               "columns: source index, i, j, P_ij, peak 2 Re sum W D")
 
 
 if __name__ == "__main__":

@@ -49,9 +49,10 @@ def _gpu_loss_grad(pk, obs, srcs, fluxes, targets, prec):
 
 def _check(g_lm, g_f, ref_lm, ref_f, label, flux_scale=None):
     """Direction components relative to the larger of the source's two; the
-    flux component relative to itself, or to ``flux_scale[s]`` where given
-    (the sum of the magnitudes of the terms of dL/dflux = 2 sum r P, which
-    cancel near the optimum)."""
+    flux component relative to itself, or to ``flux_scale[s]`` where given:
+    the sum of the magnitudes of the terms of dL/dflux = 2 sum r P (FP64
+    oracle), which cancel near the optimum, so that a patch error of 1e-6
+    of its peak can exceed 1e-4 of the cancelled sum."""
     for s in range(len(ref_lm)):
         scale = np.max(np.abs(ref_lm[s]))
         err = np.max(np.abs(g_lm[s] - ref_lm[s])) / scale
@@ -110,6 +111,7 @@ def _golden_case(tag, obs):
     srcs = ps.sources(3, seed=0)[:meta["n_src"]]
     T = np.load(os.path.join(GOLD, tag + "_targets.npy"))
     ref = np.load(os.path.join(GOLD, tag + "_grad.npy"))
+    meta["flux_scale"] = np.load(os.path.join(GOLD, tag + "_fluxscale.npy"))
     return srcs, [s.flux for s in srcs], list(T), ref, meta
 
 
@@ -120,7 +122,7 @@ def test_backward_config3_first_64_baselines(pk, prec):
     assert obs.K == meta["K"]
     L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, T, prec)
     assert abs(L - meta["loss"]) <= 1e-3 * meta["loss"]
-    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3/64bl {prec}")
+    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3/64bl {prec}", flux_scale=meta["flux_scale"])
 
 
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
@@ -133,7 +135,7 @@ def test_backward_config3_full(pk, prec):
     assert obs.K == meta["K"]
     L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, T, prec)
     assert abs(L - meta["loss"]) <= 1e-3 * meta["loss"]
-    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3 {prec}")
+    _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3 {prec}", flux_scale=meta["flux_scale"])
 
 
 def test_backward_zero_cotangent_and_repeatability(pk):
