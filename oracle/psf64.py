@@ -88,11 +88,25 @@ def bin_table(obs) -> BinTable:
 
 
 def _bin_freq(obs, tab: BinTable) -> np.ndarray:
-    """Mean channel frequency of every bin (the bin's centre frequency)."""
+    """Mean channel frequency of every bin (the bin's centre frequency).
+
+    Each distinct channel range [c0, c1) is averaged once with np.mean and
+    the value is repeated for every bin with that range (baseline by
+    baseline: a baseline's frequency bins repeat in every time bin)."""
     out = np.empty(len(tab.c0))
-    pairs, inv = np.unique(np.stack([tab.c0, tab.c1], axis=1), axis=0, return_inverse=True)
-    means = np.array([np.mean(obs.freq_hz[a:b]) for a, b in pairs])
-    out[:] = means[inv.ravel()]
+    cache = {}
+    n_ch = len(obs.freq_hz)
+    for b in range(obs.uvw_m.shape[0]):
+        k0, k1 = int(obs.bl_koff[b]), int(obs.bl_koff[b + 1])
+        nc = int(obs.bl_bin[b, 1])
+        n_fb = -(-n_ch // nc)
+        fm = []
+        for F in range(n_fb):
+            key = (F * nc, min(n_ch, (F + 1) * nc))
+            if key not in cache:
+                cache[key] = np.mean(obs.freq_hz[key[0]:key[1]])
+            fm.append(cache[key])
+        out[k0:k1] = np.tile(np.array(fm), (k1 - k0) // n_fb)
     return out
 
 
