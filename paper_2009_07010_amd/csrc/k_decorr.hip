@@ -43,13 +43,13 @@ namespace psf {
 // Several sources per launch: grid row y handles source y, whose direction
 // is read from device memory at dirs + y * dir_stride (l0, m0 as the first
 // two doubles) when dirs is given, and whose records start y * rec_stride
-// elements into uvp_out and c_out.
-__global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
+// elements into rec_out and c_out.
+__global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0, double dl, double dm,
                                                 const double* __restrict__ dirs, int64_t dir_stride,
                                                 int64_t rec_stride,
                                                 const float2* __restrict__ D_in,
                                                 float2* __restrict__ D_out,
-                                                double2* __restrict__ uvp_out,
+                                                BinRec* __restrict__ rec_out,
                                                 float2* __restrict__ c_out,
                                                 float2* __restrict__ coef_out) {
   // No fused multiply-add in this kernel: the two products of the phase
@@ -60,8 +60,10 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   if (dirs != nullptr) {
     l0 = dirs[blockIdx.y * dir_stride];
     m0 = dirs[blockIdx.y * dir_stride + 1];
+    dl = dirs[blockIdx.y * dir_stride + 4];
+    dm = dirs[blockIdx.y * dir_stride + 5];
   }
-  if (uvp_out != nullptr) uvp_out += blockIdx.y * rec_stride;
+  if (rec_out != nullptr) rec_out += blockIdx.y * rec_stride;
   if (c_out != nullptr) c_out += blockIdx.y * rec_stride;
   const BinRef r = locate_bin(o.koff, o.tboff, o.bl_bin, o.n_bl, o.n_t, o.n_ch, k);
   const double n0 = sqrt(1.0 - l0 * l0 - m0 * m0);
@@ -118,7 +120,15 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   const double s = nu_k * kInvCLight;
   const double u = uc * s, v = vc * s, w = wc * s;
   const double up = u - w * l0 / n0, vp = v - w * m0 / n0;
-  if (uvp_out != nullptr) uvp_out[k] = make_double2(up, vp);
+  if (rec_out != nullptr) {
+    BinRec r;
+    r.up = up;
+    r.vp = vp;
+    const cf32 sa = expi_turns(up * (16.0 * dl)), sb = expi_turns(vp * (16.0 * dm));
+    r.step_a = make_float2(sa.re, sa.im);
+    r.step_b = make_float2(sb.re, sb.im);
+    rec_out[k] = r;
+  }
   const float W = o.W[k];
   const float cre = W * dre, cim = W * dim;
   if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
@@ -143,21 +153,22 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   }
 }
 
-hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
-                         double2* uvp_out, float2* c_out, float2* coef_out, hipStream_t stream) {
+hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
+                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
-  hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0,
-                     m0, nullptr, int64_t(0), int64_t(0), D_in, D_out, uvp_out, c_out, coef_out);
+  hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0, dl, dm,
+                     nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
   return hipGetLastError();
 }
 
 hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t dir_stride, int n_src,
-                                 double2* uvp_out, float2* c_out, int64_t rec_stride, hipStream_t stream) {
+                                 BinRec* rec_out, float2* c_out, int64_t rec_stride, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
   hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(n_src)), dim3(threads), 0,
-                     stream, o, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, nullptr, uvp_out, c_out, nullptr);
+                     stream, o, 0.0, 0.0, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, nullptr, rec_out, c_out,
+                     nullptr);
   return hipGetLastError();
 }
 

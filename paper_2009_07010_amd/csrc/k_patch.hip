@@ -11,25 +11,25 @@
 // k-slice, keeps the tile in matrix-core accumulators, and writes a partial
 // tile; K-f adds the partials in slice order (deterministic).
 //
-// A workgroup has 12 waves: 8 contraction waves and 4 generator waves, two
-// and one per SIMD, so the matrix core (contraction) and the vector ALU
-// (phase factors) of a SIMD work at the same time.  Per chunk of 16
-// visibilities
-//   * the generator waves write the next chunk's A and B columns for the
-//     tile into one of two LDS buffers, in the exact operand layout of the
-//     MFMA instruction (K-b), and
-//   * the contraction waves run the MFMAs of the current chunk from the
-//     other buffer (K-c),
-// and one barrier per chunk separates writers from readers.  Each generator
-// thread owns one visibility and every 8th row of A or of B: one FP64-reduced
-// seed exp(2 pi i u' x_r0) and one FP64-reduced step exp(2 pi i u' 8 dl),
-// then FP32 complex multiplication along the rows.
+// A workgroup has 8 waves, two per SIMD.  Every wave both contracts and
+// generates: per chunk of 16 visibilities it
+//   * runs the MFMAs of its sub-tile of the output tile on the current
+//     chunk's A and B columns from one of two LDS buffers (K-c), and,
+//     interleaved with those MFMAs in the same instruction stream,
+//   * writes its share of the next chunk's A or B columns into the other
+//     buffer, in the exact operand layout of the MFMA instruction (K-b),
+// and one barrier per chunk separates writers from readers.  Interleaving
+// lets the vector ALU work of the phase factors issue while the matrix core
+// executes.  Waves 0-3 generate A (tile rows), waves 4-7 B (tile columns),
+// so each SIMD holds one of each: a generating thread owns one visibility
+// and every 16th row, with one FP64-reduced seed and one FP64-reduced step
+// of 16 rows, then FP32 complex multiplication along the rows.
 //
 // Tile and wave shapes are compile-time: a tile of TBI x TBJ 16x16 blocks is
-// cut into a 2 x 4 grid of contraction-wave sub-tiles whose block counts
-// differ by at most one per side; each wave runs the loop instantiated for
-// its own shape (chosen by a uniform switch on the wave index), so the
-// contraction is straight-line code with no per-block conditions.
+// cut into eight sub-tiles (wave_shape); each wave runs the loop
+// instantiated for its own shape and axis (chosen by a uniform switch on the
+// wave index), so the contraction is straight-line code with no per-block
+// conditions.
 //
 // Two-level accumulation: matrix-core accumulators collect a run of
 // flush_chunks chunks and are then added into a second FP32 tile, the
@@ -59,19 +59,17 @@ typedef __attribute__((address_space(3))) uint8_t lds_t;
 // group of 8 visibilities, 16 floats: 64 bytes, i.e. half of the 32 banks.
 // The four 16-byte chunks of row r are stored XOR-swizzled by (r >> 1) & 3,
 // which makes the 16-byte operand reads of 8 consecutive rows hit 32
-// distinct banks.  A generator thread writes the rows of one residue class
-// mod 8 (rows r0, r0 + 8, ...), so its swizzle is constant, and the two
-// 16-lane groups of a half-wave write adjacent rows, i.e. opposite bank
-// halves.
+// distinct banks.  A generating thread writes the rows of one residue class
+// mod 16 (rows r0, r0 + 16, ...), so its swizzle is constant, and the 16-lane
+// groups of a wave write adjacent rows.
 constexpr int kRowBytes = 64;
 constexpr int kChunk = 16;    // visibilities per LDS chunk
-constexpr int kPrefetch = 4;  // chunks of per-bin records held ahead by a generator thread
 
 __device__ __forceinline__ int swz(int row, int chunk) { return (chunk ^ ((row >> 1) & 3)) << 4; }
 
 // What the tile body needs of one work item's source.
 struct TileArgs {
-  const double2* uvp;
+  const BinRec* rec;
   const float2* c;
   double l_first, dl, l0, m_first, dm, m0;
   int flush_chunks;
@@ -131,7 +129,13 @@ struct TileGeom {
   static constexpr int APL = (F32 ? 2 : 1) * GA, BPL = (F32 ? 2 : 1) * GB;
   static constexpr int NPL = TWO ? 2 : 1;
   static constexpr int BUF = NPL * (APL + BPL);
-  static constexpr int LDS = 2 * BUF;
+  // Chunk buffers.  2: the chunk being contracted and the chunk being
+  // generated.  3: also the next chunk, complete one barrier early, so that
+  // its first operand fragments can be read ahead of the barrier (measured
+  // slower on the 257-pixel tiles, kept selectable).
+  static constexpr int NBUF = 2;
+  static constexpr int LDS = NBUF * BUF;
+  static_assert(LDS <= 160 * 1024, "LDS of a workgroup exceeds 160 KiB");
 };
 
 // Sub-tile of one contraction wave: m x n blocks at block (i0, j0) of the
@@ -176,16 +180,143 @@ __device__ __forceinline__ void store_data_guard() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Contraction wave W of a TBI x TBJ tile.  Its second-level accumulators
+// True if the eight contraction-wave sub-tiles cover every block of the tile
+// exactly once and no sub-tile holds more than 20 blocks (80 accumulator
+// registers).
+template <int TBI, int TBJ>
+constexpr bool wave_shapes_ok() {
+  int cover[TBI * TBJ] = {};
+  for (int w = 0; w < 8; ++w) {
+    const WaveShape s = wave_shape(TBI, TBJ, w);
+    if (s.m * s.n > 64 || s.i0 + s.m > TBI || s.j0 + s.n > TBJ) return false;
+    int nb = 0;
+    for (int r = 0; r < s.m; ++r)
+      for (int c = 0; c < s.n; ++c)
+        if ((s.mask >> (r * s.n + c)) & 1) {
+          ++cover[(s.i0 + r) * TBJ + s.j0 + c];
+          ++nb;
+        }
+    if (nb > 20) return false;
+  }
+  for (int b = 0; b < TBI * TBJ; ++b)
+    if (cover[b] != 1) return false;
+  return true;
+}
+
+// Phase-factor generation of one wave (K-b).  Waves 0-3 write A (tile rows),
+// waves 4-7 write B (tile columns), so each SIMD (waves w and w + 4) holds
+// one of each.  Thread (visibility gv, class rc = 4 (w mod 4) + lane / 16)
+// writes rows rc, rc + 16, ... of its axis for every chunk: one FP64-reduced
+// seed at row rc and the bin's 16-row step (formed once per bin with the
+// records), then FP32 complex multiplication along the rows.  A row class is constant mod 8, so the
+// thread's swizzle is constant.  Per-bin records are fetched three chunks
+// ahead into a shift register.
+template <int PREC, int TBI, int TBJ, bool IS_A>
+struct Gen {
+  using G = TileGeom<PREC, TBI, TBJ>;
+  static constexpr int R = IS_A ? TBI : TBJ;  // rows per thread
+  static constexpr int GSTRIDE = IS_A ? G::GA : G::GB;
+  static constexpr int GOFF = IS_A ? 0 : G::NPL * G::APL;
+  static constexpr int GLO = IS_A ? G::APL : G::BPL;
+  static constexpr int P = 3;  // chunks of records held ahead
+
+  int gv, rc;
+  double pos0;
+  const BinRec* recs;
+  const float2* cptr;
+  int64_t kb, ke;
+  double rf[P];   // u' (A) or v' (B)
+  cf32 rst[P];    // 16-row step
+  cf32 rcc[P];    // W D (A)
+  bool rok[P];
+  cf32 z, zs;
+  lds_t* plane;
+
+  __device__ __forceinline__ Gen(const TileArgs& a, int wave, int bi0, int bj0, int64_t kb_, int64_t ke_) {
+    const int lane = threadIdx.x & 63;
+    gv = lane & 15;
+    rc = 4 * (wave & 3) + (lane >> 4);
+    pos0 = IS_A ? (a.l_first + (16 * bi0 + rc) * a.dl) - a.l0 : (a.m_first + (16 * bj0 + rc) * a.dm) - a.m0;
+    recs = a.rec;
+    cptr = a.c;
+    kb = kb_;
+    ke = ke_;
+  }
+  // Branch-free fetch (a conditional load would make the compiler wait for
+  // it at once): past the end of the slice the last bin is read and its
+  // weight is zeroed when used.  B needs no zeroing, A's zero weight already
+  // cancels those terms.
+  __device__ __forceinline__ void fetch(int64_t n, double& f, cf32& st, cf32& cc, bool& ok) const {
+    const int64_t kg = kb + n * kChunk + gv;
+    ok = kg < ke;
+    const int64_t kc = ok ? kg : ke - 1;
+    const BinRec* r = recs + kc;
+    f = IS_A ? r->up : r->vp;
+    const float2 s = IS_A ? r->step_a : r->step_b;
+    st = {s.x, s.y};
+    if (IS_A) {
+      const float2 c = cptr[kc];
+      cc = {c.x, c.y};
+    }
+  }
+  __device__ __forceinline__ void prime() {
+#pragma unroll
+    for (int j = 0; j < P; ++j) fetch(j, rf[j], rst[j], rcc[j], rok[j]);
+  }
+  // Seed and step of the chunk held in ring slot 0, to be written into
+  // buffer buf (the step comes with the record).
+  __device__ __forceinline__ void begin(lds_t* smem, int buf) {
+    z = expi_turns(rf[0] * pos0);
+    zs = rst[0];
+    if (IS_A) {
+      const cf32 cc = rok[0] ? rcc[0] : cf32{0.f, 0.f};
+      z = conj(cmul(cc, z));
+      zs = conj(zs);
+    }
+    plane = smem + buf * G::BUF + GOFF;
+  }
+  // Rows [q0, q1) of the current chunk (q0, q1 fold to constants once the
+  // caller's loops are unrolled).
+  __device__ __forceinline__ void rows(int q0, int q1) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q < q0 || q >= q1) continue;
+      store_operand<PREC>(plane, GLO, GSTRIDE, rc + 16 * q, gv, z);
+      z = cmul(z, zs);
+    }
+  }
+  // Shift the ring by one chunk and fetch chunk n into its last slot.
+  __device__ __forceinline__ void advance(int64_t n) {
+#pragma unroll
+    for (int j = 0; j + 1 < P; ++j) {
+      rf[j] = rf[j + 1];
+      rst[j] = rst[j + 1];
+      rcc[j] = rcc[j + 1];
+      rok[j] = rok[j + 1];
+    }
+    fetch(n, rf[P - 1], rst[P - 1], rcc[P - 1], rok[P - 1]);
+  }
+};
+
+// One wave on one work item: the contraction of its sub-tile (K-c) for
+// chunk n, interleaved with the generation of its rows of chunk n + 1 into
+// the other LDS buffer, then one barrier.  Its second-level accumulators
 // are its blocks of the workgroup's partial slab in global memory, laid out
 // [block][lane][4] in accumulator lane order (block = tile row block * TBJ +
 // tile column block).
 template <int PREC, int TBI, int TBJ, int W>
-__device__ __forceinline__ void mfma_wave(const TileArgs& a, lds_t* smem, int64_t nch, float* __restrict__ slab) {
+__device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb, int64_t ke,
+                                          float* __restrict__ slab) {
+  static_assert(wave_shapes_ok<TBI, TBJ>(), "contraction waves must cover the tile once");
   using G = TileGeom<PREC, TBI, TBJ>;
   constexpr WaveShape S = wave_shape(TBI, TBJ, W);
   constexpr int M = S.m, N = S.n, WI0 = S.i0, WJ0 = S.j0;
   constexpr auto on = [](int r, int c) { return ((S.mask >> (r * N + c)) & 1) != 0; };
+  constexpr bool IS_A = W < 4;
+  using Gn = Gen<PREC, TBI, TBJ, IS_A>;
+  constexpr int R = Gn::R;
+  // generation rows spread over the contraction steps of a chunk
+  constexpr int NSTEP = G::F32 ? 2 * N : N + M;
   typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
   typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
   const int lane = threadIdx.x & 63;
@@ -205,26 +336,82 @@ __device__ __forceinline__ void mfma_wave(const TileArgs& a, lds_t* smem, int64_
     store_data_guard();
   };
 
+  const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
+  Gn gen(a, W, bi0, bj0, kb, ke);
+  // With NBUF chunk buffers, chunks 0 .. NBUF - 2 are generated before the
+  // loop; in the loop, chunk n is contracted from buffer n mod NBUF while
+  // chunk n + NBUF - 1 is generated into buffer (n + NBUF - 1) mod NBUF.
+  // With three buffers the first operand fragments of chunk n + 1 (complete
+  // since the previous barrier) are read ahead of the barrier.
+  constexpr int NB = G::NBUF;
+  if (nch > 0) {
+    gen.prime();
+#pragma unroll
+    for (int b = 0; b + 1 < NB; ++b) {
+      gen.begin(smem, b);
+      gen.rows(0, R);
+      gen.advance(Gn::P + b);
+    }
+  }
   f32x4 acc[M][N];
 #pragma unroll
   for (int r = 0; r < M; ++r)
 #pragma unroll
     for (int c = 0; c < N; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  __syncthreads();  // chunk 0 generated
+  __syncthreads();  // the first NBUF - 1 chunks generated
+
+  auto buf_at = [&](int b) { return static_cast<const lds_t*>(smem + b * G::BUF); };
+  auto ldA = [&](const lds_t* Ah, int plane, int r) {
+    return *reinterpret_cast<const lds_bf16x8*>(Ah + plane * G::APL + (16 * (WI0 + r) + lr) * kRowBytes + rd);
+  };
+  auto ldB = [&](const lds_t* Ah, int plane, int c) {
+    return *reinterpret_cast<const lds_bf16x8*>(Ah + G::NPL * G::APL + plane * G::BPL + (16 * (WJ0 + c) + lr) * kRowBytes +
+                                                rd);
+  };
+  auto ldA32 = [&](const lds_t* Ah, int g, int r) {
+    return *reinterpret_cast<const lds_f32x4*>(Ah + g * G::GA + (16 * (WI0 + r) + lr) * kRowBytes + rd);
+  };
+  // first operand fragments of the chunk about to be contracted
+  bf16x8 pah[M], pbh = {}, pbl = {};
+  f32x4 pav[M];
+  auto prefetch = [&](const lds_t* Ah) {
+    if constexpr (G::F32) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) pav[r] = ldA32(Ah, 0, r);
+    } else {
+#pragma unroll
+      for (int r = 0; r < M; ++r) pah[r] = ldA(Ah, 0, r);
+      pbh = ldB(Ah, 0, 0);
+      if constexpr (G::TWO) pbl = ldB(Ah, 1, 0);
+    }
+  };
+  int cur = 0;  // buffer of chunk n
+  if (NB == 3 && nch > 0) prefetch(buf_at(0));
 
   const int64_t flush = a.flush_chunks;
   for (int64_t run0 = 0; run0 < nch; run0 += flush) {
     const int64_t run1 = min(nch, run0 + flush);
     for (int64_t n = run0; n < run1; ++n) {
-      const lds_t* Ah = smem + static_cast<int>(n & 1) * G::BUF;
+      const int nxt = cur + 1 == NB ? 0 : cur + 1;
+      const int gen_buf = NB == 2 ? nxt : (nxt + 1 == NB ? 0 : nxt + 1);
+      const lds_t* Ah = buf_at(cur);
       const lds_t* Bh = Ah + G::NPL * G::APL;
+      if (NB == 2) prefetch(Ah);
+      // Chunk n + NBUF - 1 (past the end near the last chunk: zero weights,
+      // written into an idle buffer and never read).
+      gen.begin(smem, gen_buf);
+      int step = 0;
+      auto gen_step = [&]() {
+        gen.rows((step * R) / NSTEP, ((step + 1) * R) / NSTEP);
+        ++step;
+        __builtin_amdgcn_sched_barrier(0);
+      };
       if constexpr (G::F32) {
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
           f32x4 av[M];
 #pragma unroll
-          for (int r = 0; r < M; ++r)
-            av[r] = *reinterpret_cast<const lds_f32x4*>(Ah + g * G::GA + (16 * (WI0 + r) + lr) * kRowBytes + rd);
+          for (int r = 0; r < M; ++r) av[r] = g == 0 ? pav[r] : ldA32(Ah, g, r);
 #pragma unroll
           for (int c = 0; c < N; ++c) {
             const f32x4 bv =
@@ -235,54 +422,50 @@ __device__ __forceinline__ void mfma_wave(const TileArgs& a, lds_t* smem, int64_
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                   acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], bv[e], acc[r][c], 0, 0, 0);
+            gen_step();
           }
         }
       } else {
         // pass 1: A_hi x (B_hi, B_lo), keeping every B_hi fragment;
-        // pass 2: A_lo x B_hi.  Operand registers: 4 (M + N + 1).
-        // Loads run one column (pass 1) or one row (pass 2) ahead of their
-        // MFMAs; scheduling barriers keep the compiler from hoisting more
-        // loads than that, which would not fit the register budget.
-        auto ldA = [&](int plane, int r) {
-          return *reinterpret_cast<const lds_bf16x8*>(Ah + plane * G::APL + (16 * (WI0 + r) + lr) * kRowBytes + rd);
-        };
-        auto ldB = [&](int plane, int c) {
-          return *reinterpret_cast<const lds_bf16x8*>(Bh + plane * G::BPL + (16 * (WJ0 + c) + lr) * kRowBytes + rd);
-        };
-        bf16x8 ah[M], bh[N];
-#pragma unroll
-        for (int r = 0; r < M; ++r) ah[r] = ldA(0, r);
-        bf16x8 nbh = ldB(0, 0), nbl = {};
-        if constexpr (G::TWO) nbl = ldB(1, 0);
+        // pass 2: A_lo x B_hi.  Loads run one column (pass 1) or one row
+        // (pass 2) ahead of their MFMAs.
+        bf16x8 bh[N];
+        bf16x8 nbh = pbh, nbl = pbl;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
           bh[c] = nbh;
           const bf16x8 bl = nbl;
           if (c + 1 < N) {
-            nbh = ldB(0, c + 1);
-            if constexpr (G::TWO) nbl = ldB(1, c + 1);
+            nbh = ldB(Ah, 0, c + 1);
+            if constexpr (G::TWO) nbl = ldB(Ah, 1, c + 1);
           }
 #pragma unroll
           for (int r = 0; r < M; ++r) {
             if (!on(r, c)) continue;
-            acc[r][c] = mfma16<PREC>(ah[r], bh[c], acc[r][c]);
-            if constexpr (G::TWO) acc[r][c] = mfma16<PREC>(ah[r], bl, acc[r][c]);
+            acc[r][c] = mfma16<PREC>(pah[r], bh[c], acc[r][c]);
+            if constexpr (G::TWO) acc[r][c] = mfma16<PREC>(pah[r], bl, acc[r][c]);
           }
-          __builtin_amdgcn_sched_barrier(0);
+          gen_step();
         }
         if constexpr (G::TWO) {
-          bf16x8 nal = ldA(1, 0);
+          bf16x8 nal = ldA(Ah, 1, 0);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
             const bf16x8 al = nal;
-            if (r + 1 < M) nal = ldA(1, r + 1);
+            if (r + 1 < M) nal = ldA(Ah, 1, r + 1);
 #pragma unroll
             for (int c = 0; c < N; ++c)
               if (on(r, c)) acc[r][c] = mfma16<PREC>(al, bh[c], acc[r][c]);
-            __builtin_amdgcn_sched_barrier(0);
+            gen_step();
           }
+        } else {
+#pragma unroll
+          for (int r = 0; r < M; ++r) gen_step();
         }
       }
+      gen.advance(n + (NB - 1) + Gn::P);
+      if (NB == 3 && n + 1 < nch) prefetch(buf_at(nxt));
+      cur = nxt;
       __syncthreads();
     }
     // second level: fold this run into the slab (the first run initialises
@@ -308,119 +491,6 @@ __device__ __forceinline__ void mfma_wave(const TileArgs& a, lds_t* smem, int64_
       for (int c = 0; c < N; ++c)
         if (on(r, c)) slab_st((WI0 + r) * TBJ + (WJ0 + c), acc[r][c]);
   }
-}
-
-// Generator waves: waves 8 and 9 write A (tile rows), waves 10 and 11 write
-// B (tile columns).  Thread (visibility gv, class rc) of an axis writes rows
-// rc, rc + 8, rc + 16, ... of that axis for every chunk: one seed at row rc
-// and one step of 8 rows, both FP64-reduced.
-template <int PREC, int TBI, int TBJ, bool IS_A>
-__device__ __forceinline__ void gen_wave(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
-                                         int64_t ke, int64_t nch) {
-  using G = TileGeom<PREC, TBI, TBJ>;
-  constexpr int R = IS_A ? G::RA : G::RB;
-  const int pt = threadIdx.x - (IS_A ? 512 : 640);
-  const int gv = pt & 15, rc = pt >> 4;  // rc in 0..7
-  const double pos0 = IS_A ? (a.l_first + (16 * bi0 + rc) * a.dl) - a.l0 : (a.m_first + (16 * bj0 + rc) * a.dm) - a.m0;
-  const double d8 = 8.0 * (IS_A ? a.dl : a.dm);
-  constexpr int gstride = IS_A ? G::GA : G::GB;
-  constexpr int goff = IS_A ? 0 : G::NPL * G::APL;
-  constexpr int glo = IS_A ? G::APL : G::BPL;
-
-  // Branch-free fetch (a conditional load would make the compiler wait for
-  // it at once): past the end of the slice the last bin is read and its
-  // weight is zeroed when used.  B needs no zeroing, A's zero weight already
-  // cancels those terms.
-  const double* uv_axis = reinterpret_cast<const double*>(a.uvp) + (IS_A ? 0 : 1);
-  auto fetch = [&](int64_t n, double& f, cf32& cc, bool& ok) {
-    const int64_t kg = kb + n * kChunk + gv;
-    ok = kg < ke;
-    const int64_t kc = ok ? kg : ke - 1;
-    f = uv_axis[2 * kc];
-    if (IS_A) {
-      const float2 c = a.c[kc];
-      cc = {c.x, c.y};
-    }
-  };
-  auto generate = [&](int buf, double f, cf32 cc, bool ok) {
-    cf32 z = expi_turns(f * pos0);
-    cf32 zs = expi_turns(f * d8);
-    if (IS_A) {
-      if (!ok) cc = {0.f, 0.f};
-      z = conj(cmul(cc, z));
-      zs = conj(zs);
-    }
-    lds_t* plane = smem + buf * G::BUF + goff;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      store_operand<PREC>(plane, glo, gstride, rc + 8 * q, gv, z);
-      z = cmul(z, zs);
-    }
-  };
-
-  // Records are fetched kPrefetch chunks ahead into a register ring (slot =
-  // chunk mod kPrefetch), which hides the latency of the global loads.
-  constexpr int P = kPrefetch;
-  double ring_f[P];
-  cf32 ring_c[P];
-  bool ring_ok[P];
-  if (nch > 0) {
-#pragma unroll
-    for (int j = 0; j < P; ++j) fetch(j, ring_f[j], ring_c[j], ring_ok[j]);
-    generate(0, ring_f[0], ring_c[0], ring_ok[0]);
-    fetch(P, ring_f[0], ring_c[0], ring_ok[0]);
-  }
-  __syncthreads();
-  // Chunk n+1 is generated while the contraction waves consume chunk n.  The
-  // last iteration writes a chunk past the end (zero weights) into the idle
-  // buffer; nothing reads it.
-  for (int64_t n = 0; n < nch; n += P) {
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      if (n + j >= nch) break;
-      const int slot = (j + 1) % P;  // holds chunk n + j + 1 (n is a multiple of P)
-      generate(static_cast<int>((n + j + 1) & 1), ring_f[slot], ring_c[slot], ring_ok[slot]);
-      fetch(n + j + 1 + P, ring_f[slot], ring_c[slot], ring_ok[slot]);
-      __syncthreads();
-    }
-  }
-}
-
-// True if the eight contraction-wave sub-tiles cover every block of the tile
-// exactly once and no sub-tile holds more than 20 blocks (80 accumulator
-// registers).
-template <int TBI, int TBJ>
-constexpr bool wave_shapes_ok() {
-  int cover[TBI * TBJ] = {};
-  for (int w = 0; w < 8; ++w) {
-    const WaveShape s = wave_shape(TBI, TBJ, w);
-    if (s.m * s.n > 64 || s.i0 + s.m > TBI || s.j0 + s.n > TBJ) return false;
-    int nb = 0;
-    for (int r = 0; r < s.m; ++r)
-      for (int c = 0; c < s.n; ++c)
-        if ((s.mask >> (r * s.n + c)) & 1) {
-          ++cover[(s.i0 + r) * TBJ + s.j0 + c];
-          ++nb;
-        }
-    if (nb > 20) return false;
-  }
-  for (int b = 0; b < TBI * TBJ; ++b)
-    if (cover[b] != 1) return false;
-  return true;
-}
-
-// The work of one wave role on one work item.  Roles: 0-7 contraction
-// sub-tiles (wave_shape), 8 the A generator (waves 8, 9), 10 the B
-// generator (waves 10, 11); one generator wave per SIMD.
-template <int PREC, int TBI, int TBJ, int ROLE>
-__device__ __forceinline__ void role_body(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb,
-                                          int64_t ke, float* slab) {
-  static_assert(wave_shapes_ok<TBI, TBJ>(), "contraction waves must cover the tile once");
-  const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
-  if constexpr (ROLE < 8)
-    mfma_wave<PREC, TBI, TBJ, ROLE>(a, smem, nch, slab);
-  else
-    gen_wave<PREC, TBI, TBJ, ROLE == 8>(a, smem, bi0, bj0, kb, ke, nch);
 }
 
 // ---------------------------------------------------------------- tile plan
@@ -519,7 +589,7 @@ __device__ __forceinline__ Item decode_item(const BatchArgs& a, karg_plan* plans
   it.kb = static_cast<int64_t>(split) * kps;
   it.ke = min(a.K, it.kb + kps);
   it.slab = p.partial + tile_first_elem(t, ti, tj) + static_cast<int64_t>(split) * slab_elems(t, r, c);
-  it.ta.uvp = p.uvp;
+  it.ta.rec = p.rec;
   it.ta.c = p.c;
   it.ta.flush_chunks = a.flush_chunks;
   if (p.dir != nullptr) {
@@ -550,10 +620,10 @@ __device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, 
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const Item it = decode_item(a, plans, item);
     switch (it.type) {
-      case 0: role_body<PREC, I0, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      case 1: role_body<PREC, I0, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      case 2: role_body<PREC, I1, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      default: role_body<PREC, I1, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 0: wave_item<PREC, I0, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 1: wave_item<PREC, I0, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 2: wave_item<PREC, I1, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      default: wave_item<PREC, I1, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
     }
   }
 }
@@ -562,7 +632,7 @@ __device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, 
 // launch's sources.  Template arguments are the two tile heights and the two
 // tile widths (in blocks) of its tile family.
 template <int PREC, int I0, int I1, int J0, int J1>
-__global__ __attribute__((amdgpu_flat_work_group_size(768, 768), amdgpu_waves_per_eu(3, 3)))
+__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
 void k_patch(BatchArgs a) {
   constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
   constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
@@ -583,10 +653,7 @@ void k_patch(BatchArgs a) {
     case 4: role_loop<PREC, I0, I1, J0, J1, 4>(a, plans, smem); break;
     case 5: role_loop<PREC, I0, I1, J0, J1, 5>(a, plans, smem); break;
     case 6: role_loop<PREC, I0, I1, J0, J1, 6>(a, plans, smem); break;
-    case 7: role_loop<PREC, I0, I1, J0, J1, 7>(a, plans, smem); break;
-    case 8:
-    case 9: role_loop<PREC, I0, I1, J0, J1, 8>(a, plans, smem); break;
-    default: role_loop<PREC, I0, I1, J0, J1, 10>(a, plans, smem); break;
+    default: role_loop<PREC, I0, I1, J0, J1, 7>(a, plans, smem); break;
   }
 }
 
@@ -665,13 +732,13 @@ template <int PREC>
 static hipError_t launch_family(const BatchArgs& a, dim3 grid, hipStream_t stream) {
   const TilePlan& t = a.src[0].tp;
   if (t.tbi[0] == 9 && t.tbi[1] == 8)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17>), grid, dim3(768), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 9)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(768), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 5)
-    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(768), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(512), 0, stream, a);
   else
-    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(768), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(512), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -159,19 +159,19 @@ PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wg
 
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
   size_t b = 0;
-  b += align_up(static_cast<size_t>(o->K) * sizeof(double2), 256);  // (u', v')
+  b += align_up(static_cast<size_t>(o->K) * sizeof(BinRec), 256);  // (u', v')
   b += align_up(static_cast<size_t>(o->K) * sizeof(float2), 256);   // c = W D
   b += align_up(p.partial_elems * sizeof(float), 256);
   return b;
 }
 
 // ------------------------------------------------------------------ contraction
-SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const double2* uvp, const float2* c, float* partial,
+SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec, const float2* c, float* partial,
                  float* P, const double* dir) {
   SrcPlan p;
   p.tp = plan.tp;
   p.item0 = 0;
-  p.uvp = uvp;
+  p.rec = rec;
   p.c = c;
   p.partial = partial;
   p.P = P;
@@ -198,13 +198,13 @@ int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_finalize launch");
 }
 
-int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
+int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const BinRec* rec,
              const float2* c, float* partial, float* P, hipStream_t s) {
   BatchArgs a;
   a.n_src = 1;
   a.flush_chunks = kFlushChunks;
   a.K = obs->K;
-  a.src[0] = src_plan(h_src, plan, uvp, c, partial, P, nullptr);
+  a.src[0] = src_plan(h_src, plan, rec, c, partial, P, nullptr);
   a.n_items = tile_plan_items(plan.tp);
   return run_batch(prec, a, a.n_items, s);
 }
@@ -321,8 +321,8 @@ int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream)
   if (D == nullptr && obs->K > 0) return fail(PSF_EINVAL, "D is NULL");
   if ((st = check_device()) != PSF_OK) return st;
   if (obs->K == 0) return PSF_OK;
-  hipError_t e = launch_decorr(view(obs), l0, m0, nullptr, reinterpret_cast<float2*>(D), nullptr, nullptr,
-                               nullptr, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_decorr(view(obs), l0, m0, 0.0, 0.0, nullptr, reinterpret_cast<float2*>(D), nullptr,
+                               nullptr, nullptr, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_decorr launch");
 }
 
@@ -342,19 +342,19 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
   const hipStream_t s = static_cast<hipStream_t>(stream);
 
   uint8_t* w = static_cast<uint8_t*>(ws);
-  double2* uvp = reinterpret_cast<double2*>(w);
-  w += align_up(static_cast<size_t>(obs->K) * sizeof(double2), 256);
+  BinRec* rec = reinterpret_cast<BinRec*>(w);
+  w += align_up(static_cast<size_t>(obs->K) * sizeof(BinRec), 256);
   float2* c = reinterpret_cast<float2*>(w);
   w += align_up(static_cast<size_t>(obs->K) * sizeof(float2), 256);
   float* partial = reinterpret_cast<float*>(w);
 
   hipError_t e = hipSuccess;
   if (obs->K > 0) {
-    e = launch_decorr(view(obs), h_src->l0, h_src->m0, reinterpret_cast<const float2*>(D), nullptr, uvp, c,
-                      nullptr, s);
+    e = launch_decorr(view(obs), h_src->l0, h_src->m0, h_src->dl, h_src->dm, reinterpret_cast<const float2*>(D),
+                      nullptr, rec, c, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
   }
-  return contract(obs, h_src, plan, prec, uvp, c, partial, P, s);
+  return contract(obs, h_src, plan, prec, rec, c, partial, P, s);
 }
 
 }  // extern "C"

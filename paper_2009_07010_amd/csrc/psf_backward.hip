@@ -64,7 +64,7 @@ hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, d
 
 namespace {
 struct BackwardLayout {
-  size_t uvp, coef, partial, pe, total;
+  size_t rec, coef, partial, pe, total;
 };
 
 BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
@@ -75,8 +75,8 @@ BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_src
   }
   BackwardLayout L;
   const size_t K = static_cast<size_t>(o->K);
-  L.uvp = 0;
-  L.coef = L.uvp + align_up(K * sizeof(double2), 256);
+  L.rec = 0;
+  L.coef = L.rec + align_up(K * sizeof(BinRec), 256);
   L.partial = L.coef + align_up(5 * K * sizeof(float2), 256);
   L.pe = L.partial + align_up(partial * sizeof(float), 256);
   L.total = L.pe + align_up(5 * pix * sizeof(float), 256);
@@ -109,7 +109,7 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
   if ((st = check_device()) != PSF_OK) return st;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   uint8_t* w = static_cast<uint8_t*>(ws);
-  double2* uvp = reinterpret_cast<double2*>(w + L.uvp);
+  BinRec* rec = reinterpret_cast<BinRec*>(w + L.rec);
   float2* coef = reinterpret_cast<float2*>(w + L.coef);
   float* partial = reinterpret_cast<float*>(w + L.partial);
   float* pe = reinterpret_cast<float*>(w + L.pe);
@@ -119,12 +119,12 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
     const int64_t pix = static_cast<int64_t>(src.nl) * src.nm;
     hipError_t e;
     if (K > 0) {
-      e = launch_decorr(view(obs), src.l0, src.m0, nullptr, nullptr, uvp, nullptr, coef, s);
+      e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, nullptr, coef, s);
       if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
     }
     const PatchPlan plan = plan_patch(obs, &src, prec, kTargetWorkgroups);
     for (int q = 0; q < 5; ++q)
-      if ((st = contract(obs, &src, plan, prec, uvp, coef + q * K, partial, pe + q * pix, s)) != PSF_OK) return st;
+      if ((st = contract(obs, &src, plan, prec, rec, coef + q * K, partial, pe + q * pix, s)) != PSF_OK) return st;
     e = launch_grad_reduce(G_all + src.out_off, pe, src.nl, src.nm, src.l_first, src.dl, src.l0, src.m_first,
                            src.dm, src.m0, grad_lm + 2 * n, s);
     if (e != hipSuccess) return hip_fail(e, "k_grad_reduce launch");

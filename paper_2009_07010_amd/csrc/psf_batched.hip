@@ -104,7 +104,7 @@ struct Group {
 };
 
 int group_capacity(const psf_obs* o) {
-  const size_t rec = static_cast<size_t>(std::max<int64_t>(o->K, 1)) * (sizeof(double2) + sizeof(float2));
+  const size_t rec = static_cast<size_t>(std::max<int64_t>(o->K, 1)) * (sizeof(BinRec) + sizeof(float2));
   return static_cast<int>(std::max<size_t>(1, std::min<size_t>(kMaxBatch, kRecordBudget / rec)));
 }
 
@@ -151,7 +151,7 @@ GroupPlan plan_group(const psf_obs* o, const psf_src* h, const Group& g, int pre
 }
 
 size_t records_bytes(const psf_obs* o) {
-  return align_up(static_cast<size_t>(o->K) * sizeof(double2), 256) +
+  return align_up(static_cast<size_t>(o->K) * sizeof(BinRec), 256) +
          align_up(static_cast<size_t>(o->K) * sizeof(float2), 256);
 }
 
@@ -189,14 +189,14 @@ int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* 
     for (int q = 0; q < a.n_src; ++q) {
       const int s = g.idx[q];
       uint8_t* r = base + q * rec;
-      double2* uvp = reinterpret_cast<double2*>(r);
-      float2* c = reinterpret_cast<float2*>(r + align_up(static_cast<size_t>(obs->K) * sizeof(double2), 256));
+      BinRec* rec = reinterpret_cast<BinRec*>(r);
+      float2* c = reinterpret_cast<float2*>(r + align_up(static_cast<size_t>(obs->K) * sizeof(BinRec), 256));
       const double* dir = reinterpret_cast<const double*>(d + s);
       if (obs->K > 0) {
-        hipError_t e = launch_decorr_sources(ov, dir, 0, 1, uvp, c, 0, st);
+        hipError_t e = launch_decorr_sources(ov, dir, 0, 1, rec, c, 0, st);
         if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
       }
-      a.src[q] = src_plan(&h[s], gp.plans[q], uvp, c, partial + poff, P_all + h[s].out_off, dir);
+      a.src[q] = src_plan(&h[s], gp.plans[q], rec, c, partial + poff, P_all + h[s].out_off, dir);
       a.src[q].item0 = item0;
       item0 += tile_plan_items(gp.plans[q].tp);
       poff += align_up(gp.plans[q].partial_elems, 64);
@@ -286,8 +286,8 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
   if (ws == nullptr || ws_bytes < need)
     return fail(PSF_EWORKSPACE, "psf_autotune needs %zu workspace bytes, got %zu", need, ws_bytes);
   uint8_t* w = static_cast<uint8_t*>(ws);
-  double2* uvp = reinterpret_cast<double2*>(w);
-  float2* c = reinterpret_cast<float2*>(w + align_up(static_cast<size_t>(obs->K) * sizeof(double2), 256));
+  BinRec* rec = reinterpret_cast<BinRec*>(w);
+  float2* c = reinterpret_cast<float2*>(w + align_up(static_cast<size_t>(obs->K) * sizeof(BinRec), 256));
   float* partial = reinterpret_cast<float*>(w + records_bytes(obs));
   float* P = reinterpret_cast<float*>(w + records_bytes(obs) + align_up(part * sizeof(float), 256));
 
@@ -302,7 +302,9 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
   int rc = PSF_OK;
   for (size_t f = 0; f < fams.size() && rc == PSF_OK; ++f) {
     const psf_src& src = h_srcs[rep[f]];
-    if (obs->K > 0 && (e = launch_decorr(view(obs), src.l0, src.m0, nullptr, nullptr, uvp, c, nullptr, s)) != hipSuccess) {
+    if (obs->K > 0 &&
+        (e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, c, nullptr, s)) !=
+            hipSuccess) {
       rc = hip_fail(e, "k_decorr launch");
       break;
     }
@@ -316,7 +318,7 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
         a.n_src = 1;
         a.flush_chunks = fl;
         a.K = obs->K;
-        a.src[0] = src_plan(&src, plan, uvp, c, partial, P, nullptr);
+        a.src[0] = src_plan(&src, plan, rec, c, partial, P, nullptr);
         a.n_items = tile_plan_items(plan.tp);
         const int64_t n_wg = std::min<int64_t>(a.n_items, kComputeUnits);
         constexpr int kReps = 3;

@@ -39,10 +39,10 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 
 // The contraction and finalise of one patch from per-bin records (u', v')
 // and coefficients c (c_k = W_k D_k for the patch itself).
-int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const double2* uvp,
+int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const BinRec* rec,
              const float2* c, float* partial, float* P, hipStream_t s);
 
-SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const double2* uvp, const float2* c, float* partial,
+SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec, const float2* c, float* partial,
                  float* P, const double* dir);
 // Contraction (n_wg persistent workgroups) and finalise of the sources of a.
 int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s);

@@ -19,6 +19,15 @@ struct ObsView {
   int n_bl, n_t, n_ch;
 };
 
+// Per-bin record of one source that the contraction streams: the w-shifted
+// bin-centre coordinates and the phase factors of a 16-pixel step along each
+// axis of the source's pixel grid, exp(2 pi i u' 16 dl) and
+// exp(2 pi i v' 16 dm).
+struct BinRec {
+  double up, vp;          // u'_k, v'_k in wavelengths
+  float2 step_a, step_b;  // FP64-reduced, FP32 sin/cos
+};
+
 enum Prec : int { kFP32 = 0, kSplitBF16 = 1, kSplitFP16 = 2, kPlainBF16 = 3 };
 
 // Tiling of one patch.  Row tiles come in two heights (ti_a tiles of tbi[0]
@@ -42,7 +51,7 @@ struct TilePlan {
 struct SrcPlan {
   TilePlan tp;
   int64_t item0;
-  const double2* uvp;  // [K] (u'_k, v'_k) in wavelengths
+  const BinRec* rec;  // [K] per-bin records
   const float2* c;     // [K] W_k D_k (or an adjoint coefficient vector)
   float* partial;      // partial slabs, see TilePlan
   float* P;            // output patch [nl][nm]
@@ -72,13 +81,14 @@ constexpr double kAdjointScale = 1.0 / 4096.0;
 
 // coef_out (optional, [5][K]): the adjoint coefficient vectors e0..e4 (see
 // k_decorr.hip) times kAdjointScale; needs D_in == nullptr.
-hipError_t launch_decorr(const ObsView& o, double l0, double m0, const float2* D_in, float2* D_out,
-                         double2* uvp_out, float2* c_out, float2* coef_out, hipStream_t stream);
-// Records of n_src sources in one launch: source y's direction is read from
-// device memory (dirs + y dir_stride: l0, m0), its records are written at
-// uvp_out / c_out + y rec_stride.
+hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
+                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream);
+// Records of n_src sources in one launch: source y's direction and grid are
+// read from device memory (dirs + y dir_stride, laid out as psf_src: l0, m0,
+// l_first, m_first, dl, dm), its records are written at
+// rec_out / c_out + y rec_stride.
 hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t dir_stride, int n_src,
-                                 double2* uvp_out, float2* c_out, int64_t rec_stride, hipStream_t stream);
+                                 BinRec* rec_out, float2* c_out, int64_t rec_stride, hipStream_t stream);
 // dLoss/d(l0, m0) of one source from G = dLoss/dP and the five derivative
 // patches Pe [5][nl][nm] of the coefficient vectors e0..e4, FP64, written
 // to grad[0..1].
