@@ -108,16 +108,18 @@ ObsView view(const psf_obs* o) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Cost of one 16-visibility chunk of each tile type of a tile plan, in SIMD
-// cycles as measured on MI355X: the larger of the matrix-core time of the
-// busiest SIMD's two contraction waves and the vector time of the busiest
-// generator wave.
+// cycles on MI355X: matrix-core time of the busiest SIMD's two waves plus
+// the vector time of its phase-factor rows (one A-row and one B-row wave,
+// about 10 instructions per row and 100 per chunk for seeds and records,
+// 4.7 cycles each).  Measured kernels behave closer to the sum of the two
+// than to their maximum.
 static void chunk_costs(const TilePlan& t, int prec, double cost[2][2]) {
   const double mfma_per_block = prec == PSF_FP32 ? 256.0 : prec == PSF_PLAIN_BF16 ? 16.0 : 48.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c]);
-      const double gen = 4.7 * (8.0 * 2.0 * std::max(t.tbi[r], t.tbj[c]) + 60.0);
-      cost[r][c] = std::max(mf, gen);
+      const double gen = 4.7 * (10.0 * (t.tbi[r] + t.tbj[c]) + 100.0);
+      cost[r][c] = mf + gen;
     }
 }
 
