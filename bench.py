@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--prec", default="split_bf16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baselines", type=int, default=128,
+    ap.add_argument("--cpu-baselines", type=int, default=512,
                     help="baselines in the CPU-reference sample")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many steps of --prec (for rocprofv3) and print nothing else")
