@@ -157,6 +157,48 @@ def decorr(obs, l0: float, m0: float, sign: float = -1.0) -> np.ndarray:
     return (re + 1j * im) / tab.n
 
 
+def _step(a: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """Per-sample step of a sampled quantity over samples [lo, hi): the mean
+    step between the bin's first and last sample, or, for a one-sample bin,
+    the step to its neighbour (zero when the axis has one sample)."""
+    n_all = a.shape[0]
+    if hi - lo > 1:
+        return (a[hi - 1] - a[lo]) / (hi - lo - 1)
+    if n_all == 1:
+        return np.zeros_like(a[lo])
+    return a[lo + 1] - a[lo] if lo + 1 < n_all else a[lo] - a[lo - 1]
+
+
+def decorr_sinc(obs, l0: float, m0: float) -> np.ndarray:
+    """Method 1, the uv-plane approximation [section 3.1]: the distortion of
+    bin k replaced by the product of two sincs, sinc(dPsi/2) sinc(dPhi/2),
+    where dPsi is the phase change 2 pi du.l0 across the bin's time interval
+    at its centre frequency and dPhi the change across its frequency
+    interval at its centre time (l0 = (l0, m0): the method is 2-D, w is
+    dropped).  sinc(x) = sin(x)/x.  Real, float64 [K].
+
+    Reading (the paper defines the interval by its start and end, not by
+    samples): a bin of n samples spaced by s covers n s, so the change across
+    it is n times the per-sample step of the track (in time) or of the
+    channel frequency (in frequency), the step taken from the bin's own first
+    and last samples (from its neighbour for a one-sample bin).
+    """
+    tab = bin_table(obs)
+    nu = _bin_freq(obs, tab)
+    L2 = np.array([l0, m0])
+    out = np.empty(len(tab.b))
+    for k in range(len(tab.b)):
+        b = int(tab.b[k])
+        t0, t1, c0, c1 = int(tab.t0[k]), int(tab.t1[k]), int(tab.c0[k]), int(tab.c1[k])
+        du_time = (t1 - t0) * _step(obs.uvw_m[b], t0, t1)[:2] * (nu[k] / C_LIGHT)       # wavelengths
+        dnu = (c1 - c0) * _step(obs.freq_hz, c0, c1)
+        du_freq = obs.uvw_c_m[int(tab.tb[k])][:2] * (dnu / C_LIGHT)                     # wavelengths
+        x_t = math.pi * float(du_time @ L2)
+        x_f = math.pi * float(du_freq @ L2)
+        out[k] = np.sinc(x_t / math.pi) * np.sinc(x_f / math.pi)
+    return out
+
+
 def decorr_with_grad(obs, l0: float, m0: float):
     """D_k and its derivatives with respect to l0 and m0.
 
