@@ -114,6 +114,15 @@ int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs
  * turns before FP32 sin/cos.  Needs no workspace. */
 int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream);
 
+/* Method 1 of the paper, the uv-plane approximation [section 3.1]: per bin
+ * the product sinc(dPsi/2) sinc(dPhi/2) of the phase changes across the
+ * bin's time interval (at its centre frequency) and across its frequency
+ * interval (at its centre time), 2-D (w dropped), sinc(x) = sin(x)/x.  A bin
+ * of n samples spaced by s is taken to cover n s.  Only the end rows of each
+ * bin are read.  Written like psf_decorr (D[k][0] = value, D[k][1] = 0), so
+ * psf_patch with this D gives the Method-1 PSF.  Needs no workspace. */
+int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* stream);
+
 /* The distorted PSF patch of one source [section 2.3, distorted-PSF
  * equation], P [nl][nm] float.  D is [K][2] from psf_decorr, or NULL to
  * compute it inside the call.  h_src is a host pointer. */

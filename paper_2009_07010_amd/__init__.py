@@ -51,6 +51,7 @@ _SIGNATURES = {
     "psf_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc),
                                            ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "psf_decorr": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
+    "psf_decorr_sinc": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
     "psf_patch": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P, _P,
                                  ctypes.c_size_t, _P]),
     "psf_patch_batched": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
@@ -122,6 +123,10 @@ def psf_workspace_bytes(obs: PsfObs, h_srcs, prec) -> int:
 
 def psf_decorr(obs: PsfObs, l0: float, m0: float, D_ptr: int, stream: int) -> None:
     _check(lib().psf_decorr(ctypes.byref(obs), l0, m0, D_ptr, stream))
+
+
+def psf_decorr_sinc(obs: PsfObs, l0: float, m0: float, D_ptr: int, stream: int) -> None:
+    _check(lib().psf_decorr_sinc(ctypes.byref(obs), l0, m0, D_ptr, stream))
 
 
 def psf_patch(obs: PsfObs, h_src: PsfSrc, D_ptr: Optional[int], prec, P_ptr: int, ws_ptr: int,
@@ -223,6 +228,15 @@ def decorr(dobs: DeviceObservation, l0: float, m0: float, out=None):
     torch = _torch()
     D = torch.empty((dobs.K, 2), dtype=torch.float32, device=dobs.device) if out is None else out
     psf_decorr(dobs.struct, float(l0), float(m0), D.data_ptr(), _stream_handle())
+    return torch.view_as_complex(D)
+
+
+def decorr_sinc(dobs: DeviceObservation, l0: float, m0: float, out=None):
+    """Method-1 (sinc) decorrelation factors as a complex64 tensor [K]
+    (imaginary parts zero); pass as ``D`` to ``patch`` for the Method-1 PSF."""
+    torch = _torch()
+    D = torch.empty((dobs.K, 2), dtype=torch.float32, device=dobs.device) if out is None else out
+    psf_decorr_sinc(dobs.struct, float(l0), float(m0), D.data_ptr(), _stream_handle())
     return torch.view_as_complex(D)
 
 

@@ -173,3 +173,63 @@ hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t d
 }
 
 }  // namespace psf
+
+namespace psf {
+
+// Method 1, the uv-plane approximation [section 3.1]: D_k replaced by
+// sinc(dPsi/2) sinc(dPhi/2), dPsi = 2 pi du.(l0, m0) across the bin's time
+// interval at its centre frequency, dPhi the same across its frequency
+// interval at its centre time (2-D: w is dropped), sinc(x) = sin(x)/x.  A
+// bin of n samples spaced by s covers n s: the change across it is n times
+// the per-sample step, taken from the bin's first and last samples (from a
+// neighbour for a one-sample bin; zero if the axis has one sample).  Only
+// the bin's end rows are read, not its samples.  FP64; written as (D, 0).
+__device__ __forceinline__ double sinc_of(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+__global__ __launch_bounds__(256) void k_decorr_sinc(ObsView o, double l0, double m0, float2* __restrict__ D_out) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= o.K) return;
+  const BinRef r = locate_bin(o.koff, o.tboff, o.bl_bin, o.n_bl, o.n_t, o.n_ch, k);
+  const double nu_k = bin_freq(o.freq, r.c0, r.c1);
+  const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
+  // per-sample step in time (metres)
+  const int nt = r.t1 - r.t0;
+  int ta, tb2;
+  double div;
+  if (nt > 1) {
+    ta = r.t0;
+    tb2 = r.t1 - 1;
+    div = nt - 1;
+  } else if (o.n_t > 1) {
+    ta = r.t0 + 1 < o.n_t ? r.t0 : r.t0 - 1;
+    tb2 = ta + 1;
+    div = 1.0;
+  } else {
+    ta = tb2 = r.t0;
+    div = 1.0;
+  }
+  const double su = (row[3 * tb2] - row[3 * ta]) / div, sv = (row[3 * tb2 + 1] - row[3 * ta + 1]) / div;
+  // per-channel frequency step (Hz)
+  const int nc = r.c1 - r.c0;
+  double sf;
+  if (nc > 1)
+    sf = (o.freq[r.c1 - 1] - o.freq[r.c0]) / (nc - 1);
+  else if (o.n_ch > 1)
+    sf = r.c0 + 1 < o.n_ch ? o.freq[r.c0 + 1] - o.freq[r.c0] : o.freq[r.c0] - o.freq[r.c0 - 1];
+  else
+    sf = 0.0;
+  const double pi = 3.141592653589793;
+  const double x_t = pi * (nt * (su * l0 + sv * m0) * (nu_k * kInvCLight));
+  const double uc = o.uvw_c[3 * r.tb], vc = o.uvw_c[3 * r.tb + 1];
+  const double x_f = pi * ((uc * l0 + vc * m0) * (nc * sf * kInvCLight));
+  D_out[k] = make_float2(static_cast<float>(sinc_of(x_t) * sinc_of(x_f)), 0.0f);
+}
+
+hipError_t launch_decorr_sinc(const ObsView& o, double l0, double m0, float2* D_out, hipStream_t stream) {
+  const int threads = 256;
+  const int64_t blocks = (o.K + threads - 1) / threads;
+  hipLaunchKernelGGL(k_decorr_sinc, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0, D_out);
+  return hipGetLastError();
+}
+
+}  // namespace psf

@@ -328,6 +328,19 @@ int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream)
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_decorr launch");
 }
 
+int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* stream) {
+  g_msg[0] = 0;
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if (!std::isfinite(l0) || !std::isfinite(m0) || l0 * l0 + m0 * m0 >= 1.0)
+    return fail(PSF_EINVAL, "bad direction (%g, %g)", l0, m0);
+  if (D == nullptr && obs->K > 0) return fail(PSF_EINVAL, "D is NULL");
+  if ((st = check_device()) != PSF_OK) return st;
+  if (obs->K == 0) return PSF_OK;
+  hipError_t e = launch_decorr_sinc(view(obs), l0, m0, reinterpret_cast<float2*>(D), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_decorr_sinc launch");
+}
+
 int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec, float* P, void* ws,
               size_t ws_bytes, void* stream) {
   g_msg[0] = 0;

@@ -83,6 +83,8 @@ constexpr double kAdjointScale = 1.0 / 4096.0;
 // k_decorr.hip) times kAdjointScale; needs D_in == nullptr.
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
                          float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream);
+// Method-1 (sinc) decorrelation factors, written as (D, 0).
+hipError_t launch_decorr_sinc(const ObsView& o, double l0, double m0, float2* D_out, hipStream_t stream);
 // Records of n_src sources in one launch: source y's direction and grid are
 // read from device memory (dirs + y dir_stride, laid out as psf_src: l0, m0,
 // l_first, m_first, dl, dm), its records are written at

@@ -281,7 +281,7 @@ def bda_bins(bl_enu: np.ndarray, max_t: int = 64, max_c: int = 8) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# the five workloads
+# the workloads
 # --------------------------------------------------------------------------
 CONFIG_NAMES = {
     1: "tiny: 7 ants in 1 km, 600 x 1 s, 1 ch at 1.4 GHz, 30-sample bins, 65^2 at 2\"",
@@ -289,16 +289,17 @@ CONFIG_NAMES = {
     3: "differentiation: config-2 data, 16 sources, 129^2 at 1.5\"",
     4: "precision: 64 ants, 1800 x 2 s, 64 ch 0.9-1.7 GHz, 5x2 bins, 64 sources, 257^2",
     5: "batched BDA: 64 ants, 14400 x 1 s, 64 ch 1.3-1.5 GHz, BDA bins, 256 sources",
+    6: "the paper's averaging setup: 64 ants, 7200 x 1 s, 120 x 50 kHz ch at 1.4 GHz, 20 s x 2 MHz bins",
 }
 
 
 def observation(config: int, seed: int = 0, bin_samples: Optional[int] = None) -> Observation:
-    """The observation of workload ``config`` (1..5).
+    """The observation of workload ``config`` (1..6).
 
     ``bin_samples`` overrides the time-bin length of workload 1 (30 by
     default; 20 gives the 630-bin variant).
     """
-    g = rng(config if config != 3 else 2, STREAM_LAYOUT, seed)
+    g = rng(config if config not in (3, 6) else 2, STREAM_LAYOUT, seed)
     if config == 1:
         ants = layout_disc(7, 1000.0, g)
         nt = 30 if bin_samples is None else int(bin_samples)
@@ -315,6 +316,11 @@ def observation(config: int, seed: int = 0, bin_samples: Optional[int] = None) -
         _, bl_enu = baselines(ants)
         return make_observation(ants, 14400, 1.0, channel_centres(1.3e9, 1.5e9, 64),
                                 bda_bins(bl_enu), weight_rng=wr, name="config5")
+    if config == 6:
+        # 2 h at 1 s, 6 MHz of 120 x 50 kHz channels centred on 1.4 GHz,
+        # averaged to 20 s x 2 MHz (40 channels), natural weights
+        return make_observation(ants, 7200, 1.0, channel_centres(1.397e9, 1.403e9, 120), [20, 40],
+                                name="config6")
     raise ValueError(f"unknown workload {config}")
 
 

@@ -130,6 +130,10 @@ def test_decorr_bad_direction(L):
     o = fake_obs()
     st, _ = status_of(L.psf_decorr, ctypes.byref(o), 0.8, 0.8, FAKE, None)
     assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_decorr_sinc, ctypes.byref(o), 0.8, 0.8, FAKE, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_decorr_sinc, ctypes.byref(o), 0.01, 0.01, None, None)
+    assert st == pk.PSF_EINVAL
     st, _ = status_of(L.psf_decorr, ctypes.byref(o), float("inf"), 0.0, FAKE, None)
     assert st == pk.PSF_EINVAL
 
