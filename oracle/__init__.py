@@ -16,5 +16,5 @@ from .psf64 import (  # noqa: F401
     C_LIGHT, BinTable, bin_table, bin_centres_lambda, decorr, decorr_sinc, decorr_with_grad,
     decorr_brute, wshift, pixel_offsets, patch_factored, patch_brute, patch_pixels,
     patch_fullw, effective_psf_closed_form, peak_normalised_error, loss_value,
-    loss_grad_analytic, loss_grad_fd,
+    loss_grad_analytic, loss_grad_fd, hogbom_clean,
 )

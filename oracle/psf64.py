@@ -457,3 +457,33 @@ def loss_grad_fd(obs, srcs, fluxes, targets, h: float = 1e-3 * math.pi / (180 * 
                 vals.append(float(np.sum(r * r)))
             g[n, a] = (vals[0] - vals[1]) / (2.0 * h)
     return g
+
+
+# --------------------------------------------------------------------------
+# deconvolution with position-dependent PSFs [Algorithm 2, Hogbom CLEAN]
+# --------------------------------------------------------------------------
+def hogbom_clean(obs, grid, dirty: np.ndarray, gain: float, n_iter: int, threshold: float = 0.0,
+                 D_of=None):
+    """Hogbom CLEAN in which every minor cycle computes the distorted PSF at
+    the current peak [Algorithm 2]: find the peak pixel of |residual|, form
+    P_d at that direction on the image grid (``grid``: l_first, m_first, dl,
+    dm, nl, nm), subtract gain * peak * P_d / P_d(peak), record the component
+    gain * peak; stop after n_iter cycles or when |peak| < threshold.  (The
+    model update accumulates: the listing assigns it.)  The peak is the first
+    maximum in row-major order.  ``D_of(l0, m0)`` may supply the decorrelation
+    factors (default: the exact ones).  Returns (residual, [(i, j, amp)])."""
+    res = np.array(dirty, dtype=np.float64)
+    comps = []
+    for _ in range(n_iter):
+        flat = int(np.argmax(np.abs(res)))
+        i, j = divmod(flat, res.shape[1])
+        peak = res[i, j]
+        if abs(peak) < threshold:
+            break
+        l0 = grid.l_first + i * grid.dl
+        m0 = grid.m_first + j * grid.dm
+        src = grid.with_direction(l0, m0)
+        P = patch_factored(obs, src, None if D_of is None else D_of(l0, m0))
+        res = res - gain * peak * P / P[i, j]
+        comps.append((i, j, gain * peak))
+    return res, comps

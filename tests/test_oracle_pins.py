@@ -423,3 +423,43 @@ def test_sinc_method_real_bounded_and_close_to_exact_on_tracks(cfg1):
     assert np.all(np.abs(Dh) <= 1.0)
     assert np.max(np.abs(Dh - D.real)) < 5e-4
     assert np.max(np.abs(Dh - D.real)) > 1e-7   # an approximation, not the same quantity
+
+
+# ---------------------------------------------------------------- Hogbom CLEAN [Algorithm 2]
+def _image_grid(n=33, cell=2.0 * ps.ARCSEC, centre=(0.004, -0.003)):
+    return ps.Source.centred(centre[0], centre[1], n, cell)
+
+
+@pytest.mark.parametrize("gain", [1.0, 0.3])
+def test_clean_single_source_residual_is_geometric(cfg1, gain):
+    """A dirty image that is one distorted PSF (source on a pixel centre): each
+    cycle finds the same pixel and removes the fraction gain of what is
+    left, so after n cycles the residual is (1 - gain)^n of the dirty image
+    and the components sum to (1 - (1 - gain)^n) of its peak."""
+    obs, _ = cfg1
+    grid = _image_grid()
+    i0, j0 = 20, 11
+    src = grid.with_direction(grid.l_first + i0 * grid.dl, grid.m_first + j0 * grid.dm)
+    dirty = 0.7 * orc.patch_factored(obs, src)
+    n = 1 if gain == 1.0 else 6
+    res, comps = orc.hogbom_clean(obs, grid, dirty, gain, n)
+    assert [(i, j) for i, j, _ in comps] == [(i0, j0)] * n
+    assert np.max(np.abs(res - (1 - gain) ** n * dirty)) <= 1e-12 * np.max(np.abs(dirty))
+    assert abs(sum(a for _, _, a in comps) - (1 - (1 - gain) ** n) * dirty[i0, j0]) <= 1e-12 * dirty[i0, j0]
+
+
+def test_clean_two_sources_recovers_positions(cfg1):
+    """Two sources of different flux on pixel centres, far enough apart that
+    their PSFs barely overlap at the peaks: the brighter is found first and
+    both positions appear among the components."""
+    obs, _ = cfg1
+    grid = _image_grid(n=65)
+    pos = [(10, 12, 1.0), (50, 44, 0.45)]
+    dirty = sum(f * orc.patch_factored(obs, grid.with_direction(grid.l_first + i * grid.dl,
+                                                                grid.m_first + j * grid.dm))
+                for i, j, f in pos)
+    res, comps = orc.hogbom_clean(obs, grid, dirty, 0.5, 12)
+    assert comps[0][:2] == (10, 12)
+    found = {(i, j) for i, j, _ in comps}
+    assert (10, 12) in found and (50, 44) in found
+    assert np.max(np.abs(res)) < 0.2 * np.max(np.abs(dirty))
