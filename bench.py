@@ -115,6 +115,23 @@ def time_method1(pk, torch, dobs, src, prec, ws, reps=10):
             "psf_from_sinc_ms": psf_ms}
 
 
+def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
+    """Hogbom CLEAN with the distorted PSF at every peak on a 257 x 257 image
+    of this workload: three sources placed on pixels, dirty image formed by
+    the library, `cycles` minor cycles timed (each one PSF evaluation plus
+    the peak search, subtraction and one read-back)."""
+    dirty = torch.zeros((grid.nl, grid.nm), dtype=torch.float32, device="cuda")
+    for i, j, f in ((60, 70, 1.0), (180, 150, 0.5), (128, 230, 0.25)):
+        s = grid.with_direction(grid.l_first + i * grid.dl, grid.m_first + j * grid.dm)
+        dirty += f * pk.patch(dobs, s, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, comps = pk.clean_hogbom(dobs, grid, dirty, cycles, 0.1, 0.0, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"image": [grid.nl, grid.nm], "cycles": len(comps), "ms_per_cycle": dt / max(1, len(comps)) * 1e3}
+
+
 def cpu_baseline(obs, src, n_bl_sub):
     """The FP64 oracle (decorr + factored patch) on the first n_bl_sub baselines."""
     import numpy as np
@@ -208,6 +225,7 @@ def main():
                                  f"{terms} terms per launch"},
     }
     line["method1"] = time_method1(pk, torch, dobs, src, a.prec, ws)
+    line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
     print(json.dumps(line), flush=True)

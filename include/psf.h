@@ -157,6 +157,23 @@ int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                        const psf_src* d_srcs, const float* G_all, int prec,
                        double* grad_lm, void* ws, size_t ws_bytes, void* stream);
 
+/* Hogbom CLEAN with position-dependent PSFs [Algorithm 2]: up to max_iter
+ * minor cycles on the image `residual` (device, float [nl][nm] on the grid
+ * of h_grid, whose l0, m0 are ignored; in: the dirty image, out: the
+ * residual).  Each cycle takes the peak pixel of |residual| (the first
+ * maximum in row-major order), evaluates the distorted PSF of that
+ * direction on the image grid with the arithmetic prec (as psf_patch,
+ * decorrelation factors computed), subtracts gain * peak * PSF / PSF(peak)
+ * and records the component (pixel comp_i, comp_j, amplitude gain * peak;
+ * host arrays of max_iter entries; *n_comp receives the count).  Stops
+ * early when |peak| < threshold.  gain in (0, 1].  Synchronises the stream
+ * once per cycle to read the peak: not capturable.  ws sized with
+ * psf_clean_workspace_bytes. */
+int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int prec, size_t* out);
+int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t max_iter, double gain,
+                     double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
+                     int32_t* n_comp, void* ws, size_t ws_bytes, void* stream);
+
 /* Times candidate launch shapes for these sources with HIP events and
  * writes a JSON tuning table (host buffer json_out, capacity json_cap).
  * Synchronises the stream: not capturable. */

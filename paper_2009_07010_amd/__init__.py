@@ -60,6 +60,11 @@ _SIGNATURES = {
                                           _P, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
     "psf_autotune": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc),
                                     ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_size_t, _P]),
+    "psf_clean_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "psf_clean_hogbom": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P,
+                                        ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
     "psf_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "psf_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "psf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -392,3 +397,25 @@ def autotune(dobs: DeviceObservation, srcs: Sequence, prec="split_bf16", workspa
     need = psf_workspace_bytes(dobs.struct, h, prec)
     ws = (workspace or Workspace(dobs.device)).get(need)
     return psf_autotune(dobs.struct, h, prec, ws.data_ptr(), ws.numel(), _stream_handle())
+
+
+def clean_hogbom(dobs: DeviceObservation, grid, dirty, max_iter: int, gain: float = 0.1, threshold: float = 0.0,
+                 prec="split_bf16", workspace: Optional[Workspace] = None):
+    """Hogbom CLEAN with the distorted PSF at every peak (``psf_clean_hogbom``).
+    ``dirty`` is a float32 [nl, nm] image on the grid of ``grid``; returns
+    (residual tensor, list of (i, j, amplitude))."""
+    torch = _torch()
+    h = make_src(grid)
+    need = ctypes.c_size_t(0)
+    _check(lib().psf_clean_workspace_bytes(ctypes.byref(dobs.struct), ctypes.byref(h), _prec(prec),
+                                           ctypes.byref(need)))
+    ws = (workspace or Workspace(dobs.device)).get(need.value)
+    res = dirty.to(device=dobs.device, dtype=torch.float32).contiguous().clone()
+    ci = (ctypes.c_int32 * max(1, max_iter))()
+    cj = (ctypes.c_int32 * max(1, max_iter))()
+    ca = (ctypes.c_float * max(1, max_iter))()
+    n = ctypes.c_int32(0)
+    _check(lib().psf_clean_hogbom(ctypes.byref(dobs.struct), ctypes.byref(h), res.data_ptr(), int(max_iter),
+                                  float(gain), float(threshold), _prec(prec), ci, cj, ca, ctypes.byref(n),
+                                  ws.data_ptr(), ws.numel(), _stream_handle()))
+    return res, [(ci[k], cj[k], ca[k]) for k in range(n.value)]

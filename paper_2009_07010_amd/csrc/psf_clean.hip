@@ -1,0 +1,182 @@
+// Deconvolution with position-dependent PSFs [Algorithm 2, Hogbom CLEAN]:
+// every minor cycle finds the peak of |residual|, computes the distorted PSF
+// at that direction on the image grid (the same decorrelation, phase-factor
+// and contraction kernels as psf_patch), and subtracts gain * peak times the
+// PSF normalised to 1 at the peak.  The peak search and the subtraction are
+// kernels; the host reads back the peak (one synchronisation per cycle) to
+// place the next PSF.
+#include <algorithm>
+
+#include "psf_host.hpp"
+
+namespace psf {
+
+namespace {
+
+constexpr int kMaxThreads = 256;
+constexpr int kMaxBlocks = 512;
+
+struct Peak {
+  float absval;
+  float val;
+  int64_t idx;
+};
+
+// Larger |value| wins; equal |value|: the smaller index (the first maximum
+// in row-major order).
+__device__ __forceinline__ Peak better(const Peak& a, const Peak& b) {
+  if (a.absval > b.absval) return a;
+  if (b.absval > a.absval) return b;
+  return a.idx <= b.idx ? a : b;
+}
+
+__device__ Peak block_best(Peak p) {
+  __shared__ float s_abs[kMaxThreads / 64], s_val[kMaxThreads / 64];
+  __shared__ int64_t s_idx[kMaxThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    Peak q;
+    q.absval = __shfl_xor(p.absval, o);
+    q.val = __shfl_xor(p.val, o);
+    q.idx = __shfl_xor(p.idx, o);
+    p = better(p, q);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    s_abs[wave] = p.absval;
+    s_val[wave] = p.val;
+    s_idx[wave] = p.idx;
+  }
+  __syncthreads();
+  Peak r{-1.0f, 0.0f, INT64_MAX};
+  for (int w = 0; w < kMaxThreads / 64; ++w) r = better(r, Peak{s_abs[w], s_val[w], s_idx[w]});
+  return r;
+}
+
+// Per-block best of a grid-strided range; one entry per block.
+__global__ __launch_bounds__(kMaxThreads) void k_absmax_partial(const float* __restrict__ x, int64_t n,
+                                                                 Peak* __restrict__ part) {
+  Peak p{-1.0f, 0.0f, INT64_MAX};
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kMaxThreads)
+    p = better(p, Peak{fabsf(x[i]), x[i], i});
+  const Peak r = block_best(p);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_absmax_final(const Peak* __restrict__ part, int nb,
+                                                               Peak* __restrict__ out) {
+  Peak p{-1.0f, 0.0f, INT64_MAX};
+  for (int i = threadIdx.x; i < nb; i += kMaxThreads) p = better(p, part[i]);
+  const Peak r = block_best(p);
+  if (threadIdx.x == 0) *out = r;
+}
+
+// residual -= gain * peak * P / P[peak index]
+__global__ __launch_bounds__(kMaxThreads) void k_clean_subtract(float* __restrict__ res, const float* __restrict__ P,
+                                                                 int64_t n, const Peak* __restrict__ pk, float gain) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x;
+  if (i >= n) return;
+  const float scale = gain * pk->val / P[pk->idx];
+  res[i] -= scale * P[i];
+}
+
+struct CleanLayout {
+  size_t patch, P, part, peak, total;
+};
+
+CleanLayout clean_layout(const psf_obs* o, const psf_src* grid, int prec) {
+  CleanLayout L;
+  const PatchPlan plan = plan_patch(o, grid, prec, kTargetWorkgroups);
+  L.patch = 0;
+  L.P = align_up(patch_workspace(o, plan), 256);
+  L.part = L.P + align_up(static_cast<size_t>(grid->nl) * grid->nm * sizeof(float), 256);
+  L.peak = L.part + align_up(kMaxBlocks * sizeof(Peak), 256);
+  L.total = L.peak + align_up(sizeof(Peak), 256);
+  return L;
+}
+
+int validate_clean(const psf_obs* obs, const psf_src* grid, int prec) {
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = validate_src(grid, 0)) != PSF_OK) return st;
+  return PSF_OK;
+}
+
+}  // namespace
+
+}  // namespace psf
+
+using namespace psf;
+
+extern "C" {
+
+int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int prec, size_t* out) {
+  int st;
+  if ((st = validate_clean(obs, h_grid, prec)) != PSF_OK) return st;
+  if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
+  *out = clean_layout(obs, h_grid, prec).total;
+  return PSF_OK;
+}
+
+int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t max_iter, double gain,
+                     double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
+                     int32_t* n_comp, void* ws, size_t ws_bytes, void* stream) {
+  int st;
+  if ((st = validate_clean(obs, h_grid, prec)) != PSF_OK) return st;
+  if (residual == nullptr || n_comp == nullptr) return fail(PSF_EINVAL, "residual or n_comp is NULL");
+  if (max_iter < 0) return fail(PSF_EINVAL, "max_iter < 0");
+  if (max_iter > 0 && (comp_i == nullptr || comp_j == nullptr || comp_amp == nullptr))
+    return fail(PSF_EINVAL, "component arrays are NULL");
+  if (!(gain > 0.0 && gain <= 1.0)) return fail(PSF_EINVAL, "gain %g outside (0, 1]", gain);
+  if (!(threshold >= 0.0)) return fail(PSF_EINVAL, "threshold must be >= 0");
+  const CleanLayout L = clean_layout(obs, h_grid, prec);
+  if (ws == nullptr || ws_bytes < L.total)
+    return fail(PSF_EWORKSPACE, "psf_clean_hogbom needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  BinRec* rec = reinterpret_cast<BinRec*>(w);
+  float2* c = reinterpret_cast<float2*>(w + align_up(static_cast<size_t>(obs->K) * sizeof(BinRec), 256));
+  float* partial = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(c) +
+                                            align_up(static_cast<size_t>(obs->K) * sizeof(float2), 256));
+  float* P = reinterpret_cast<float*>(w + L.P);
+  Peak* part = reinterpret_cast<Peak*>(w + L.part);
+  Peak* peak = reinterpret_cast<Peak*>(w + L.peak);
+  const PatchPlan plan = plan_patch(obs, h_grid, prec, kTargetWorkgroups);
+  const int64_t n = static_cast<int64_t>(h_grid->nl) * h_grid->nm;
+  const int nb = static_cast<int>(std::min<int64_t>(kMaxBlocks, (n + kMaxThreads - 1) / kMaxThreads));
+  *n_comp = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(kMaxThreads), 0, s, residual, n, part);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kMaxThreads), 0, s, part, nb, peak);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "peak search launch");
+    Peak hp;
+    if ((e = hipMemcpyAsync(&hp, peak, sizeof(Peak), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "peak read-back");
+    if (hp.idx < 0 || hp.idx >= n || !(hp.absval >= threshold) || hp.absval == 0.0f) break;
+    const int i = static_cast<int>(hp.idx / h_grid->nm), j = static_cast<int>(hp.idx % h_grid->nm);
+    psf_src src = *h_grid;
+    src.l0 = h_grid->l_first + i * h_grid->dl;
+    src.m0 = h_grid->m_first + j * h_grid->dm;
+    if (src.l0 * src.l0 + src.m0 * src.m0 >= 1.0) return fail(PSF_EINVAL, "peak pixel outside the sky");
+    if (obs->K > 0 &&
+        (e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, c, nullptr, s)) !=
+            hipSuccess)
+      return hip_fail(e, "k_decorr launch");
+    if ((st = contract(obs, &src, plan, prec, rec, c, partial, P, s)) != PSF_OK) return st;
+    hipLaunchKernelGGL(k_clean_subtract, dim3(static_cast<unsigned>((n + kMaxThreads - 1) / kMaxThreads)),
+                       dim3(kMaxThreads), 0, s, residual, P, n, peak, static_cast<float>(gain));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_clean_subtract launch");
+    comp_i[it] = i;
+    comp_j[it] = j;
+    comp_amp[it] = static_cast<float>(gain * hp.val);
+    *n_comp = it + 1;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // extern "C"

@@ -142,3 +142,26 @@ def test_binding_raises_on_error(L):
     with pytest.raises(pk.PsfError) as ei:
         pk.psf_decorr(fake_obs(n_t=0), 0.0, 0.0, FAKE, 0)
     assert ei.value.status == pk.PSF_EINVAL
+
+
+def test_clean_argument_errors(L):
+    o, g = fake_obs(), fake_src()
+    n = ctypes.c_int32(0)
+    ci = (ctypes.c_int32 * 4)()
+    cj = (ctypes.c_int32 * 4)()
+    ca = (ctypes.c_float * 4)()
+    args = lambda res, iters, gain, thr, ws, wsb: (ctypes.byref(o), ctypes.byref(g), res, iters, gain, thr, 1, ci, cj,
+                                                  ca, ctypes.byref(n), ws, wsb, None)
+    st, _ = status_of(L.psf_clean_hogbom, *args(FAKE, 4, 0.0, 0.0, FAKE, 1 << 30))
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_clean_hogbom, *args(FAKE, 4, 1.5, 0.0, FAKE, 1 << 30))
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_clean_hogbom, *args(None, 4, 0.1, 0.0, FAKE, 1 << 30))
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_clean_hogbom, *args(FAKE, -1, 0.1, 0.0, FAKE, 1 << 30))
+    assert st == pk.PSF_EINVAL
+    st, msg = status_of(L.psf_clean_hogbom, *args(FAKE, 4, 0.1, 0.0, FAKE, 16))
+    assert st == pk.PSF_EWORKSPACE and "workspace" in msg
+    need = ctypes.c_size_t(0)
+    assert L.psf_clean_workspace_bytes(ctypes.byref(o), ctypes.byref(g), 1, ctypes.byref(need)) == 0
+    assert need.value > 65 * 65 * 4
