@@ -20,6 +20,9 @@ What is computed (paper passages in brackets):
 
   The minus sign follows the paper's forward transform [section 2.1, the
   2-D Fourier relation between sky and visibility].
+* Windowed averaging [section 2.3, the boxcar replaced by a baseline-dependent
+  window]: with separable sample weights x_s = win_t[b][t] win_c[b][c],
+  D_k = sum_s x_s exp(-2 pi i phi_s) / sum_s x_s (0 for a window summing to 0).
 * The distorted PSF is the weighted sum over averaged visibilities of their
   inverse transforms [section 2.3, distorted-PSF equation], indexed by the
   offset from the source [section 2.2, direction-dependent convolution].
@@ -137,11 +140,39 @@ def _per_baseline_phases(obs, tab, uk, b, L):
     return du @ L, du, kidx
 
 
+def _windowed(obs) -> bool:
+    return getattr(obs, "win_t", None) is not None or getattr(obs, "win_c", None) is not None
+
+
+def sample_window(obs, b: int) -> np.ndarray:
+    """Window weight of every sample of baseline b, [n_t, n_ch]: the product
+    of the time and channel windows (an axis without one is boxcar, 1)."""
+    n_t, n_ch = obs.uvw_m.shape[1], len(obs.freq_hz)
+    wt = np.ones(n_t) if obs.win_t is None else np.asarray(obs.win_t[b], np.float64)
+    wc = np.ones(n_ch) if obs.win_c is None else np.asarray(obs.win_c[b], np.float64)
+    return wt[:, None] * wc[None, :]
+
+
+def _normalise(acc: np.ndarray, wsum: np.ndarray) -> np.ndarray:
+    """acc / wsum per bin, 0 where a bin's window sums to 0."""
+    out = np.zeros_like(acc)
+    nz = wsum != 0.0
+    out[..., nz] = acc[..., nz] / wsum[nz]
+    return out
+
+
 def decorr(obs, l0: float, m0: float, sign: float = -1.0) -> np.ndarray:
     """D_k, complex128 [K]: mean over each bin's samples of exp(sign 2 pi i phi_s).
 
     sign = -1 is the paper's convention; +1 gives the literal form some
     descriptions use (then every D is conjugated and the PSF is point-mirrored).
+
+    Windowed averaging [section 2.3: the normalised boxcar of the averaging
+    integral replaced by a baseline-dependent window X_pqkr]: when the
+    observation carries window weights (``win_t`` [n_bl, n_t], ``win_c``
+    [n_bl, n_ch]) the mean becomes the window-weighted mean over the bin's
+    samples, normalised by the window's sum over the bin, and a bin whose
+    window sums to 0 gets D = 0.
     """
     tab = bin_table(obs)
     uk = bin_centres_lambda(obs, tab)
@@ -149,6 +180,16 @@ def decorr(obs, l0: float, m0: float, sign: float = -1.0) -> np.ndarray:
     K = len(tab.b)
     re = np.zeros(K)
     im = np.zeros(K)
+    if _windowed(obs):
+        wsum = np.zeros(K)
+        for b in range(obs.uvw_m.shape[0]):
+            phi, _, kidx = _per_baseline_phases(obs, tab, uk, b, L)
+            x = sample_window(obs, b)
+            e = x * np.exp(sign * 1j * TWO_PI * phi)
+            re += np.bincount(kidx.ravel(), e.real.ravel(), minlength=K)
+            im += np.bincount(kidx.ravel(), e.imag.ravel(), minlength=K)
+            wsum += np.bincount(kidx.ravel(), x.ravel(), minlength=K)
+        return _normalise(re + 1j * im, wsum)
     for b in range(obs.uvw_m.shape[0]):
         phi, _, kidx = _per_baseline_phases(obs, tab, uk, b, L)
         e = np.exp(sign * 1j * TWO_PI * phi)
@@ -183,6 +224,8 @@ def decorr_sinc(obs, l0: float, m0: float) -> np.ndarray:
     channel frequency (in frequency), the step taken from the bin's own first
     and last samples (from its neighbour for a one-sample bin).
     """
+    if _windowed(obs):
+        raise ValueError("Method 1 is the closed form of the boxcar average; the observation has windows")
     tab = bin_table(obs)
     nu = _bin_freq(obs, tab)
     L2 = np.array([l0, m0])
@@ -210,15 +253,24 @@ def decorr_with_grad(obs, l0: float, m0: float):
     n0, L = _lmn(l0, m0)
     K = len(tab.b)
     acc = np.zeros((3, K), complex)
+    win = _windowed(obs)
+    wsum = np.zeros(K)
     for b in range(obs.uvw_m.shape[0]):
         phi, du, kidx = _per_baseline_phases(obs, tab, uk, b, L)
         e = np.exp(-1j * TWO_PI * phi)
+        if win:
+            x = sample_window(obs, b)
+            e = x * e
+            wsum += np.bincount(kidx.ravel(), x.ravel(), minlength=K)
         dphi_l = du[..., 0] - du[..., 2] * l0 / n0
         dphi_m = du[..., 1] - du[..., 2] * m0 / n0
         for r, val in enumerate((e, -1j * TWO_PI * dphi_l * e, -1j * TWO_PI * dphi_m * e)):
             acc[r] += (np.bincount(kidx.ravel(), val.real.ravel(), minlength=K)
                        + 1j * np.bincount(kidx.ravel(), val.imag.ravel(), minlength=K))
-    acc /= tab.n[None, :]
+    if win:
+        acc = _normalise(acc, wsum)
+    else:
+        acc /= tab.n[None, :]
     return acc[0], acc[1], acc[2]
 
 
@@ -232,18 +284,23 @@ def decorr_brute(obs, l0: float, m0: float, negate: bool = False) -> np.ndarray:
     n0 = math.sqrt(1.0 - l0 * l0 - m0 * m0)
     tab = bin_table(obs)
     out = np.zeros(len(tab.b), complex)
+    wt = getattr(obs, "win_t", None)
+    wc = getattr(obs, "win_c", None)
     for k in range(len(tab.b)):
         b, tbrow = int(tab.b[k]), int(tab.tb[k])
         chans = range(int(tab.c0[k]), int(tab.c1[k]))
         nu_c = sum(float(obs.freq_hz[c]) for c in chans) / len(chans)
         uc = [s * float(obs.uvw_c_m[tbrow, a]) * nu_c / C_LIGHT for a in range(3)]
         acc = 0j
+        norm = 0.0
         for t in range(int(tab.t0[k]), int(tab.t1[k])):
             for c in chans:
+                x = (1.0 if wt is None else float(wt[b, t])) * (1.0 if wc is None else float(wc[b, c]))
                 us = [s * float(obs.uvw_m[b, t, a]) * float(obs.freq_hz[c]) / C_LIGHT for a in range(3)]
                 phi = (us[0] - uc[0]) * l0 + (us[1] - uc[1]) * m0 + (us[2] - uc[2]) * (n0 - 1.0)
-                acc += cmath.exp(-2j * math.pi * phi)
-        out[k] = acc / (len(chans) * (int(tab.t1[k]) - int(tab.t0[k])))
+                acc += x * cmath.exp(-2j * math.pi * phi)
+                norm += x
+        out[k] = acc / norm if norm != 0.0 else 0.0
     return out
 
 

@@ -59,6 +59,8 @@ class Observation:
     uvw_c_m: np.ndarray        # [n_tb, 3] float64 bin-centre uvw (metres)
     W: np.ndarray              # [K] float32 weights
     name: str = "custom"
+    win_t: Optional[np.ndarray] = None   # [n_bl, n_t] float32 time-window weights, None = boxcar
+    win_c: Optional[np.ndarray] = None   # [n_bl, n_ch] float32 channel-window weights, None = boxcar
 
     @property
     def n_bl(self) -> int:
@@ -380,7 +382,43 @@ def first_baselines(obs: Observation, n_bl: int) -> Observation:
     return Observation(ant_enu=obs.ant_enu, bl_ant=obs.bl_ant[:B], times_s=obs.times_s,
                        uvw_m=obs.uvw_m[:B], freq_hz=obs.freq_hz, bl_bin=obs.bl_bin[:B],
                        bl_koff=obs.bl_koff[:B + 1], bl_tboff=obs.bl_tboff[:B + 1],
-                       uvw_c_m=obs.uvw_c_m[:tb1], W=obs.W[:k1], name=f"{obs.name}[:{B}]")
+                       uvw_c_m=obs.uvw_c_m[:tb1], W=obs.W[:k1], name=f"{obs.name}[:{B}]",
+                       win_t=None if obs.win_t is None else obs.win_t[:B],
+                       win_c=None if obs.win_c is None else obs.win_c[:B])
+
+
+def _bin_position(n: int, size: np.ndarray) -> np.ndarray:
+    """Centre offset of every sample inside its bin as a fraction of the
+    bin's own span, in (-1/2, 1/2): [n_bl, n] for bins of ``size[b]``
+    samples tiling from the first sample (the last bin may be short)."""
+    idx = np.arange(n)[None, :]
+    size = np.asarray(size, np.int64)[:, None]
+    first = (idx // size) * size
+    span = np.minimum(size, n - first)
+    return (idx - first + 0.5) / span - 0.5
+
+
+def tapered_windows(obs: Observation, strength: float = 1.0, channels: bool = True) -> Observation:
+    """A copy of ``obs`` with baseline-dependent, separable averaging windows
+    (input data for windowed averaging; the paper leaves the window shape to
+    the cited window designs).  Per axis, a sample at centre offset x of its
+    bin (a fraction of the bin span) has weight (1 - a) + a cos^2(pi x),
+    a = strength |b| / max |b|: close to the boxcar on short baselines, a
+    raised cosine on the longest.  ``channels=False`` leaves the channel axis
+    boxcar."""
+    bl_enu = obs.ant_enu[obs.bl_ant[:, 1]] - obs.ant_enu[obs.bl_ant[:, 0]]
+    L = np.linalg.norm(bl_enu, axis=1)
+    a = (float(strength) * L / L.max())[:, None]
+    xt = _bin_position(obs.n_t, obs.bl_bin[:, 0])
+    win_t = ((1.0 - a) + a * np.cos(math.pi * xt) ** 2).astype(np.float32)
+    if channels:
+        xc = _bin_position(obs.n_ch, obs.bl_bin[:, 1])
+        win_c = ((1.0 - a) + a * np.cos(math.pi * xc) ** 2).astype(np.float32)
+    else:
+        win_c = None
+    return dataclasses.replace(obs, win_t=np.ascontiguousarray(win_t),
+                               win_c=None if win_c is None else np.ascontiguousarray(win_c),
+                               name=f"{obs.name}+win{strength:g}")
 
 
 # --------------------------------------------------------------------------

@@ -463,3 +463,101 @@ def test_clean_two_sources_recovers_positions(cfg1):
     found = {(i, j) for i, j, _ in comps}
     assert (10, 12) in found and (50, 44) in found
     assert np.max(np.abs(res)) < 0.2 * np.max(np.abs(dirty))
+
+
+# ---------------------------------------------------------------- windowed averaging
+def _with_windows(obs, win_t=None, win_c=None):
+    return ps.Observation(**{**obs.__dict__, "win_t": win_t, "win_c": win_c})
+
+
+def _triangle(m, n_bins):
+    """Weights 1, 2, .., m, .., 2, 1 over each bin of 2m - 1 samples."""
+    one = np.minimum(np.arange(1, 2 * m), np.arange(2 * m - 1, 0, -1)).astype(np.float32)
+    return np.tile(one, n_bins)[None, :]
+
+
+@pytest.mark.parametrize("m,d", [(2, 0.11), (4, 0.07), (6, 0.23), (9, 0.031)])
+def test_triangle_time_window_is_squared_dirichlet(m, d):
+    """The triangle of 2m - 1 samples is the convolution of two m-sample
+    boxcars, so on a linear phase ramp (step d turns per sample, bin centre
+    on the middle sample) its normalised transform is the square of the
+    m-sample Dirichlet kernel."""
+    nu, l0 = 1.4e9, 0.01
+    n = 2 * m - 1
+    obs = _with_windows(ramp_observation(3 * n, n, d * C / (nu * l0), nu=nu, axis=0), win_t=_triangle(m, 3))
+    D = orc.decorr(obs, l0, 0.0)
+    assert np.allclose(D, dirichlet(m, d) ** 2, atol=1e-12, rtol=0)
+    box = orc.decorr(_with_windows(obs), l0, 0.0)
+    assert np.max(np.abs(D - box)) > 1e-3          # the window is observable
+
+
+@pytest.mark.parametrize("m", [3, 5])
+def test_triangle_channel_window_is_squared_dirichlet(m):
+    nu, m0, dnu = 1.4e9, -0.02, 5e6
+    n = 2 * m - 1
+    obs = ramp_observation(2, 1, 0.0, nu=nu, n_ch=2 * n, bin_ch=n, dnu=dnu, u0=(300.0, 2100.0, 0.0))
+    obs = _with_windows(obs, win_c=_triangle(m, 2))
+    D = orc.decorr(obs, 0.0, m0)
+    assert np.allclose(D, dirichlet(m, 2100.0 * dnu * m0 / C) ** 2, atol=1e-12, rtol=0)
+
+
+def test_window_of_ones_is_boxcar_and_scale_free(tiny):
+    l0, m0 = 0.031, -0.017
+    box = orc.decorr(tiny, l0, m0)
+    ones = _with_windows(tiny, np.ones((tiny.n_bl, tiny.n_t), np.float32),
+                         np.ones((tiny.n_bl, tiny.n_ch), np.float32))
+    assert np.max(np.abs(orc.decorr(ones, l0, m0) - box)) < 1e-15
+    win = ps.tapered_windows(tiny)
+    Dw = orc.decorr(win, l0, m0)
+    scaled = _with_windows(win, (4.0 * win.win_t).astype(np.float32), (0.25 * win.win_c).astype(np.float32))
+    assert np.max(np.abs(orc.decorr(scaled, l0, m0) - Dw)) < 1e-15     # power-of-two scales: exact in float32
+    assert np.max(np.abs(Dw - box)) > 1e-4
+
+
+def test_delta_window_on_the_bin_centre_sample_gives_one():
+    """A window that keeps only each bin's middle sample (whose uvw is the bin
+    centre) has no smearing: D = 1 at any direction."""
+    n = 7
+    obs = ramp_observation(3 * n, n, 40.0, axis=1)
+    wt = np.zeros((1, 3 * n), np.float32)
+    wt[0, n // 2::n] = 2.0
+    D = orc.decorr(_with_windows(obs, win_t=wt), 0.02, -0.05)
+    assert np.all(D == 1.0)
+
+
+def test_zero_window_bin_has_zero_D_and_others_unchanged(tiny):
+    win = ps.tapered_windows(tiny)
+    tab = orc.bin_table(tiny)
+    k = 5
+    b, t0, t1 = int(tab.b[k]), int(tab.t0[k]), int(tab.t1[k])
+    wt = win.win_t.copy()
+    wt[b, t0:t1] = 0.0                      # every bin of baseline b in this time bin
+    z = _with_windows(win, wt, win.win_c)
+    Dz, Dw = orc.decorr(z, 0.03, 0.01), orc.decorr(win, 0.03, 0.01)
+    hit = (tab.b == b) & (tab.t0 == t0)
+    assert np.all(Dz[hit] == 0.0)
+    assert np.array_equal(Dz[~hit], Dw[~hit])
+
+
+def test_windowed_decorr_matches_explicit_loops():
+    obs = ps.tapered_windows(ps.tiny_random(4, n_ant=5, n_t=11, n_ch=7, nt=4, nc=3, bda=True), strength=0.8)
+    D = orc.decorr(obs, 0.027, 0.011)
+    Db = orc.decorr_brute(obs, 0.027, 0.011)
+    assert np.max(np.abs(D - Db)) < 1e-12
+
+
+def test_windowed_decorr_gradient_matches_fd():
+    obs = ps.tapered_windows(ps.tiny_random(2, n_t=9, n_ch=5, nt=3, nc=2))
+    l0, m0, h = 0.021, -0.013, 1e-7
+    D, dl, dm = orc.decorr_with_grad(obs, l0, m0)
+    assert np.max(np.abs(D - orc.decorr(obs, l0, m0))) < 1e-15
+    fl = (orc.decorr(obs, l0 + h, m0) - orc.decorr(obs, l0 - h, m0)) / (2 * h)
+    fm = (orc.decorr(obs, l0, m0 + h) - orc.decorr(obs, l0, m0 - h)) / (2 * h)
+    scale = max(np.max(np.abs(dl)), np.max(np.abs(dm)))
+    assert np.max(np.abs(dl - fl)) < 1e-6 * scale
+    assert np.max(np.abs(dm - fm)) < 1e-6 * scale
+
+
+def test_method1_rejects_windows(tiny):
+    with pytest.raises(ValueError):
+        orc.decorr_sinc(ps.tapered_windows(tiny), 0.01, 0.0)
