@@ -387,16 +387,26 @@ def patch_pixels(obs, src, ii, jj, D: np.ndarray = None, block: int = 1 << 20) -
     return out
 
 
-def patch_fullw(obs, src, D: np.ndarray = None, block: int = 4096) -> np.ndarray:
-    """Diagnostic: the same sum with the exact w phase w (n(l, m) - n0) instead
-    of its linearisation (not factorable, so evaluated per pixel)."""
-    if D is None:
-        D = decorr(obs, src.l0, src.m0)
-    uk = bin_centres_lambda(obs)
+def _fullw_offsets(src):
+    """x_i, y_j and n(l_i, m_j) - n0 on the patch grid (FP64)."""
     n0 = math.sqrt(1.0 - src.l0 ** 2 - src.m0 ** 2)
     x, y = pixel_offsets(src)
     X, Y = np.meshgrid(x, y, indexing="ij")
-    N = np.sqrt(1.0 - (src.l0 + X) ** 2 - (src.m0 + Y) ** 2) - n0
+    return X, Y, np.sqrt(1.0 - (src.l0 + X) ** 2 - (src.m0 + Y) ** 2) - n0
+
+
+def patch_fullw(obs, src, D: np.ndarray = None, block: int = 4096) -> np.ndarray:
+    """The patch with the exact w phase instead of its linearisation: the
+    imaging phase of a bin-centre visibility at pixel (l, m) is
+    u l + v m + w (n(l, m) - 1) [section 2.1, the visibility relation with
+    its w-term], so relative to the source
+        P_ij = sum_k W_k [D_k exp(2 pi i (u_k x_i + v_k y_j + w_k (n_ij - n0))) + c.c.]
+    with n_ij = sqrt(1 - l_i^2 - m_j^2).  Not factorable, so evaluated per
+    pixel."""
+    if D is None:
+        D = decorr(obs, src.l0, src.m0)
+    uk = bin_centres_lambda(obs)
+    X, Y, N = _fullw_offsets(src)
     c = obs.W.astype(np.float64) * D
     acc = np.zeros(X.shape, complex)
     for k0 in range(0, len(c), block):
@@ -405,6 +415,24 @@ def patch_fullw(obs, src, D: np.ndarray = None, block: int = 4096) -> np.ndarray
               + uk[sl, 2, None, None] * N[None])
         acc += np.tensordot(c[sl], np.exp(1j * TWO_PI * ph), axes=(0, 0))
     return 2.0 * acc.real
+
+
+def patch_fullw_pixels(obs, src, ii, jj, D: np.ndarray = None, block: int = 1 << 20) -> np.ndarray:
+    """``patch_fullw`` at the listed pixels only, float64 [len(ii)]."""
+    if D is None:
+        D = decorr(obs, src.l0, src.m0)
+    uk = bin_centres_lambda(obs)
+    X, Y, N = _fullw_offsets(src)
+    c = obs.W.astype(np.float64) * D
+    out = np.zeros(len(ii))
+    for n, (i, j) in enumerate(zip(ii, jj)):
+        acc = 0j
+        for k0 in range(0, len(c), block):
+            sl = slice(k0, k0 + block)
+            acc += np.sum(c[sl] * np.exp(1j * TWO_PI * (uk[sl, 0] * X[i, j] + uk[sl, 1] * Y[i, j]
+                                                           + uk[sl, 2] * N[i, j])))
+        out[n] = 2.0 * acc.real
+    return out
 
 
 def effective_psf_closed_form(obs, src) -> np.ndarray:
