@@ -88,6 +88,14 @@ typedef struct psf_obs {
   const double* uvw_c_m;    /* [n_tb][3] uvw (metres) at each time-bin centre; the
                                centre frequency of a bin is the mean of its channels */
   const float* W;           /* [K] weight of each averaged visibility */
+  /* Windowed averaging (section 2.3: the boxcar of the averaging integral
+   * replaced by a baseline-dependent window).  Optional, NULL = boxcar on
+   * that axis.  Sample (b, t, c) has weight win_t[b][t] * win_c[b][c] and
+   * D_k = sum_s x_s exp(-2 pi i phi_s) / sum_s x_s over the bin's samples;
+   * a bin whose window sums to 0 gets D_k = 0.  Weights must be finite (not
+   * checked: device memory).  psf_decorr_sinc (Method 1) rejects windows. */
+  const float* win_t;       /* [n_bl][n_t] time-window weights, or NULL */
+  const float* win_c;       /* [n_bl][n_ch] channel-window weights, or NULL */
 } psf_obs;
 
 /* One source and the absolute pixel grid of its patch: pixel (i, j) is at
@@ -102,9 +110,9 @@ typedef struct psf_src {
   int64_t out_off;
 } psf_src;
 
-/* Workspace bytes needed by psf_patch (n_src = 1), psf_patch_batched and
- * psf_patch_backward for these sources and precision.  h_srcs is a host
- * array.  Writes the size to *out (host). */
+/* Workspace bytes needed by psf_patch and psf_patch_fullw (n_src = 1),
+ * psf_patch_batched and psf_patch_backward for these sources and precision.
+ * h_srcs is a host array.  Writes the size to *out (host). */
 int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                         int prec, size_t* out);
 
@@ -156,6 +164,23 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
 int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                        const psf_src* d_srcs, const float* G_all, int prec,
                        double* grad_lm, void* ws, size_t ws_bytes, void* stream);
+
+/* The patch with the exact w phase [section 2.1: the visibility relation
+ * with its w (n - 1) term] instead of the linearised w-shift:
+ *   P_ij = sum_k W_k [D_k exp(2 pi i (u_k x_i + v_k y_j + w_k (n_ij - n0))) + c.c.]
+ * with n_ij = sqrt(1 - l_i^2 - m_j^2) and D_k computed (windows honoured).
+ * The part of the w phase beyond its linearisation, w_k q_ij, is expanded
+ * in a centred Taylor series whose terms are linearised patches with
+ * modified coefficients, each contracted with the arithmetic prec; the
+ * order follows from the range of q over the grid and a bound of |w| (a
+ * truncation bound of 1e-9 of the coefficient sum).  *n_terms (host, may be
+ * NULL) receives the number of contractions.  Fails with PSF_EINVAL when a
+ * grid corner lies outside the sky or the non-linear phase spans more than
+ * 6 rad over the patch (a patch too wide for the expansion).  Synchronises
+ * the stream once (to read the |w| bound): not capturable.  ws sized with
+ * psf_workspace_bytes; P (device, float [nl][nm]) must not overlap it. */
+int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P, int32_t* n_terms,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* Hogbom CLEAN with position-dependent PSFs [Algorithm 2]: up to max_iter
  * minor cycles on the image `residual` (device, float [nl][nm] on the grid

@@ -37,7 +37,7 @@ class PsfObs(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("K", ctypes.c_int64), ("n_tb", ctypes.c_int64),
                 ("uvw_m", ctypes.c_void_p), ("freq_hz", ctypes.c_void_p), ("bl_bin", ctypes.c_void_p),
                 ("bl_koff", ctypes.c_void_p), ("bl_tboff", ctypes.c_void_p), ("uvw_c_m", ctypes.c_void_p),
-                ("W", ctypes.c_void_p)]
+                ("W", ctypes.c_void_p), ("win_t", ctypes.c_void_p), ("win_c", ctypes.c_void_p)]
 
 
 class PsfSrc(ctypes.Structure):
@@ -52,6 +52,8 @@ _SIGNATURES = {
                                            ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "psf_decorr": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
     "psf_decorr_sinc": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
+    "psf_patch_fullw": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), ctypes.c_int, _P,
+                                       ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
     "psf_patch": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P, _P,
                                  ctypes.c_size_t, _P]),
     "psf_patch_batched": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
@@ -140,6 +142,13 @@ def psf_patch(obs: PsfObs, h_src: PsfSrc, D_ptr: Optional[int], prec, P_ptr: int
                            stream))
 
 
+def psf_patch_fullw(obs: PsfObs, h_src: PsfSrc, prec, P_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    n = ctypes.c_int32(0)
+    _check(lib().psf_patch_fullw(ctypes.byref(obs), ctypes.byref(h_src), _prec(prec), P_ptr, ctypes.byref(n),
+                                 ws_ptr, ws_bytes, stream))
+    return int(n.value)
+
+
 def psf_patch_batched(obs: PsfObs, h_srcs, d_srcs_ptr: int, prec, tuning_json: Optional[bytes], P_ptr: int,
                       ws_ptr: int, ws_bytes: int, stream: int) -> None:
     _check(lib().psf_patch_batched(ctypes.byref(obs), len(h_srcs), h_srcs, d_srcs_ptr, _prec(prec), tuning_json,
@@ -186,7 +195,8 @@ class DeviceObservation:
     """An observation's arrays resident in device memory, plus the ABI struct.
 
     ``obs`` is any object with the attributes of ``psf_synth.Observation``
-    (uvw_m, freq_hz, bl_bin, bl_koff, bl_tboff, uvw_c_m, W as numpy arrays).
+    (uvw_m, freq_hz, bl_bin, bl_koff, bl_tboff, uvw_c_m, W as numpy arrays;
+    optional averaging windows win_t [n_bl, n_t] and win_c [n_bl, n_ch]).
     """
 
     def __init__(self, obs, device="cuda"):
@@ -199,6 +209,13 @@ class DeviceObservation:
         self.bl_tboff = t(obs.bl_tboff, torch.int64)
         self.uvw_c_m = t(obs.uvw_c_m, torch.float64)
         self.W = t(obs.W, torch.float32)
+        wt, wc = getattr(obs, "win_t", None), getattr(obs, "win_c", None)
+        self.win_t = None if wt is None else t(wt, torch.float32)
+        self.win_c = None if wc is None else t(wc, torch.float32)
+        if self.win_t is not None:
+            assert tuple(self.win_t.shape) == tuple(obs.uvw_m.shape[:2]), "win_t must be [n_bl, n_t]"
+        if self.win_c is not None:
+            assert tuple(self.win_c.shape) == (obs.uvw_m.shape[0], len(obs.freq_hz)), "win_c must be [n_bl, n_ch]"
         self.n_bl, self.n_t = int(obs.uvw_m.shape[0]), int(obs.uvw_m.shape[1])
         self.n_ch = int(len(obs.freq_hz))
         self.K = int(obs.bl_koff[-1])
@@ -206,7 +223,9 @@ class DeviceObservation:
         self.device = device
         self.struct = PsfObs(self.n_bl, self.n_t, self.n_ch, 0, self.K, self.n_tb, self.uvw_m.data_ptr(),
                              self.freq_hz.data_ptr(), self.bl_bin.data_ptr(), self.bl_koff.data_ptr(),
-                             self.bl_tboff.data_ptr(), self.uvw_c_m.data_ptr(), self.W.data_ptr())
+                             self.bl_tboff.data_ptr(), self.uvw_c_m.data_ptr(), self.W.data_ptr(),
+                             None if self.win_t is None else self.win_t.data_ptr(),
+                             None if self.win_c is None else self.win_c.data_ptr())
 
 
 class Workspace:
@@ -259,6 +278,18 @@ def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, wor
         D_ptr = Dr.data_ptr()
     psf_patch(dobs.struct, hs, D_ptr, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return P
+
+
+def patch_fullw(dobs: DeviceObservation, src, prec="split_bf16", out=None, workspace: Optional[Workspace] = None):
+    """The patch with the exact w phase, float32 [nl, nm], and the number of
+    contractions its expansion took."""
+    torch = _torch()
+    hs = make_src(src)
+    need = psf_workspace_bytes(dobs.struct, (PsfSrc * 1)(hs), prec)
+    ws = (workspace or Workspace(dobs.device)).get(need)
+    P = torch.empty((int(src.nl), int(src.nm)), dtype=torch.float32, device=dobs.device) if out is None else out
+    n = psf_patch_fullw(dobs.struct, hs, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    return P, n
 
 
 def patch_backward(dobs: DeviceObservation, srcs: Sequence, G_all, prec="split_bf16",

@@ -84,6 +84,50 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
     float sre = 0.f, sim = 0.f;
     float glr = 0.f, gli = 0.f, gmr = 0.f, gmi = 0.f;
     const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
+    if (o.win_t != nullptr || o.win_c != nullptr) {
+      // Windowed averaging: sample weight x = win_t[b][t] win_c[b][c], the
+      // mean normalised by the window's sum over the bin (D = 0 for a
+      // window that sums to 0).  Separable, so the normaliser is the
+      // product of the two axis sums.
+      const float* win_tb = o.win_t != nullptr ? o.win_t + static_cast<int64_t>(r.b) * o.n_t : nullptr;
+      const float* win_cb = o.win_c != nullptr ? o.win_c + static_cast<int64_t>(r.b) * o.n_ch : nullptr;
+      float st = 0.f, sc = 0.f;
+      for (int c = r.c0; c < r.c1; ++c) sc += win_cb != nullptr ? win_cb[c] : 1.f;
+      for (int t = r.t0; t < r.t1; ++t) {
+        const float xt = win_tb != nullptr ? win_tb[t] : 1.f;
+        st += xt;
+        const double u = row[3 * t + 0], v = row[3 * t + 1], w = row[3 * t + 2];
+        const double A_t = u * l0 + v * m0 + w * Lw;
+        for (int c = r.c0; c < r.c1; ++c) {
+          const float x = xt * (win_cb != nullptr ? win_cb[c] : 1.f);
+          const double nu = o.freq[c];
+          const double phi = (A_t * nu - A_knu) * kInvCLight;
+          const cf32 e = expi_turns(-phi);
+          sre += x * e.re;
+          sim += x * e.im;
+          if (grad) {
+            const double du = (u * nu - uc * nu_k) * kInvCLight;
+            const double dv = (v * nu - vc * nu_k) * kInvCLight;
+            const double dw = (w * nu - wc * nu_k) * kInvCLight;
+            const float gl = x * static_cast<float>(du - dw * l0 / n0);
+            const float gm = x * static_cast<float>(dv - dw * m0 / n0);
+            glr += gl * e.im; gli -= gl * e.re;
+            gmr += gm * e.im; gmi -= gm * e.re;
+          }
+        }
+      }
+      const float norm = st * sc;
+      const float inv = norm != 0.f ? 1.0f / norm : 0.f;
+      dre = sre * inv;
+      dim = sim * inv;
+      if (grad) {
+        const float s = 6.283185307179586f * inv;
+        dDl_re = glr * s;
+        dDl_im = gli * s;
+        dDm_re = gmr * s;
+        dDm_im = gmi * s;
+      }
+    } else {
     for (int t = r.t0; t < r.t1; ++t) {
       const double u = row[3 * t + 0], v = row[3 * t + 1], w = row[3 * t + 2];
       const double A_t = u * l0 + v * m0 + w * Lw;
@@ -114,6 +158,7 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
       dDl_im = gli * s;
       dDm_re = gmr * s;
       dDm_im = gmi * s;
+    }
     }
   }
   if (D_out != nullptr) D_out[k] = make_float2(dre, dim);

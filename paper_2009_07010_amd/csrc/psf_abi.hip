@@ -96,6 +96,8 @@ ObsView view(const psf_obs* o) {
   v.tboff = o->bl_tboff;
   v.uvw_c = o->uvw_c_m;
   v.W = o->W;
+  v.win_t = o->win_t;
+  v.win_c = o->win_c;
   v.K = o->K;
   v.n_tb = o->n_tb;
   v.n_bl = o->n_bl;
@@ -310,6 +312,7 @@ int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs
   }
   need = std::max(need, batched_workspace(obs, n_src, h_srcs, prec));
   need = std::max(need, backward_workspace(obs, n_src, h_srcs, prec));
+  need = std::max(need, fullw_workspace(obs, n_src, h_srcs, prec));
   *out = need;
   return PSF_OK;
 }
@@ -335,6 +338,8 @@ int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* st
   if (!std::isfinite(l0) || !std::isfinite(m0) || l0 * l0 + m0 * m0 >= 1.0)
     return fail(PSF_EINVAL, "bad direction (%g, %g)", l0, m0);
   if (D == nullptr && obs->K > 0) return fail(PSF_EINVAL, "D is NULL");
+  if (obs->win_t != nullptr || obs->win_c != nullptr)
+    return fail(PSF_EINVAL, "Method 1 is the closed form of boxcar averaging: the observation has windows");
   if ((st = check_device()) != PSF_OK) return st;
   if (obs->K == 0) return PSF_OK;
   hipError_t e = launch_decorr_sinc(view(obs), l0, m0, reinterpret_cast<float2*>(D), static_cast<hipStream_t>(stream));

@@ -49,6 +49,7 @@ int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s);
 
 size_t batched_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
+size_t fullw_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 
 bool timing_on();
 hipError_t timed_launch_begin(hipStream_t s, hipEvent_t* ev0);

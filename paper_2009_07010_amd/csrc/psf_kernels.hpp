@@ -14,6 +14,8 @@ struct ObsView {
   const int64_t* tboff;   // [n_bl + 1]
   const double* uvw_c;    // [n_tb][3]
   const float* W;         // [K]
+  const float* win_t;     // [n_bl][n_t] or null (boxcar in time)
+  const float* win_c;     // [n_bl][n_ch] or null (boxcar in frequency)
   int64_t K;
   int64_t n_tb;
   int n_bl, n_t, n_ch;

@@ -136,6 +136,48 @@ def config5():
                "columns: source index, i, j, P_ij, peak 2 Re sum W D")
 
 
+def config2_windows():
+    """Workload 2 with the tapered baseline-dependent windows of
+    ``psf_synth.tapered_windows`` (strength 1): sampled D and sampled pixels
+    of the source's 257 x 257 patch, with the patch peak."""
+    obs = ps.tapered_windows(ps.observation(2, seed=0))
+    src = ps.sources(2, seed=0)[0]
+    t = time.time()
+    D = orc.decorr(obs, src.l0, src.m0)
+    ks = np.random.default_rng(0).choice(obs.K, 4096, replace=False)
+    np.save(os.path.join(HERE, "config2_seed0_win_Dsample.npy"), np.stack([ks, D[ks].real, D[ks].imag], axis=1))
+    ij = config5_pixels([src], 48)[0]
+    P = orc.patch_pixels(obs, src, ij[:, 0], ij[:, 1], D)
+    peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+    np.save(os.path.join(HERE, "config2_seed0_win_pixels.npy"),
+            np.concatenate([ij.astype(np.float64), P[:, None], np.full((len(P), 1), peak)], axis=1))
+    _meta("config2_seed0_win", config=2, seed=0, K=obs.K, windows="tapered_windows(strength=1)",
+          seconds=time.time() - t,
+          what="oracle.decorr (windowed, FP64) at 4096 sampled bins: k, Re D, Im D; oracle.patch_pixels at "
+               "sampled pixels: i, j, P_ij, peak 2 Re sum W D")
+    print("config2_windows", time.time() - t)
+
+
+def config2_fullw():
+    """Workload 2's source patch (257 x 257 at 1.5 arcsec) with the exact w
+    phase, at sampled pixels, with the linearised patch at the same pixels
+    and the patch peak."""
+    obs = ps.observation(2, seed=0)
+    src = ps.sources(2, seed=0)[0]
+    t = time.time()
+    D = orc.decorr(obs, src.l0, src.m0)
+    ij = config5_pixels([src], 48)[0]
+    Pw = orc.patch_fullw_pixels(obs, src, ij[:, 0], ij[:, 1], D)
+    Pl = orc.patch_pixels(obs, src, ij[:, 0], ij[:, 1], D)
+    peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+    np.save(os.path.join(HERE, "config2_seed0_fullw_pixels.npy"),
+            np.concatenate([ij.astype(np.float64), Pw[:, None], Pl[:, None], np.full((len(Pw), 1), peak)], axis=1))
+    _meta("config2_seed0_fullw", config=2, seed=0, K=obs.K, seconds=time.time() - t,
+          what="oracle.patch_fullw_pixels (FP64, exact w phase) at sampled pixels: i, j, P_full, "
+               "P_linearised (oracle.patch_pixels), peak 2 Re sum W D")
+    print("config2_fullw", time.time() - t)
+
+
 if __name__ == "__main__":
     todo = sys.argv[1:] or ["config2"]
     for name in todo:

@@ -138,6 +138,19 @@ def test_decorr_bad_direction(L):
     assert st == pk.PSF_EINVAL
 
 
+@pytest.mark.parametrize("field", ["win_t", "win_c"])
+def test_method1_rejects_windowed_observation(L, field):
+    o = fake_obs(**{field: FAKE})
+    st, msg = status_of(L.psf_decorr_sinc, ctypes.byref(o), 0.01, 0.01, FAKE, None)
+    assert st == pk.PSF_EINVAL and "window" in msg
+
+
+def test_obs_struct_layout_matches_header():
+    """The ctypes mirror of psf_obs: 4 int32, 2 int64, 9 pointers."""
+    assert ctypes.sizeof(pk.PsfObs) == 4 * 4 + 2 * 8 + 9 * 8
+    assert pk.PsfObs.win_c.offset == ctypes.sizeof(pk.PsfObs) - 8
+
+
 def test_binding_raises_on_error(L):
     with pytest.raises(pk.PsfError) as ei:
         pk.psf_decorr(fake_obs(n_t=0), 0.0, 0.0, FAKE, 0)
@@ -165,3 +178,22 @@ def test_clean_argument_errors(L):
     need = ctypes.c_size_t(0)
     assert L.psf_clean_workspace_bytes(ctypes.byref(o), ctypes.byref(g), 1, ctypes.byref(need)) == 0
     assert need.value > 65 * 65 * 4
+
+
+def test_fullw_host_side_errors(L):
+    o = fake_obs()
+    n = ctypes.c_int32(0)
+    outside = fake_src(l0=0.9, m0=0.0, l_first=0.9, dl=0.01, nl=20)      # far corner at l = 1.09
+    st, msg = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(outside), 1, FAKE, ctypes.byref(n),
+                        FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL and "sky" in msg
+    s = fake_src()
+    st, _ = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(s), 1, None, ctypes.byref(n), FAKE,
+                      1 << 40, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(s), 1, FAKE, ctypes.byref(n), FAKE, 16,
+                      None)
+    assert st == pk.PSF_EWORKSPACE
+    st, _ = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(s), 7, FAKE, ctypes.byref(n), FAKE,
+                      1 << 40, None)
+    assert st == pk.PSF_EINVAL

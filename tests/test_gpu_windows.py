@@ -1,0 +1,169 @@
+"""GPU parity of windowed averaging (the boxcar of the averaging integral
+replaced by baseline-dependent, separable sample windows) against the FP64
+oracle: the decorrelation factors, the patch in every accurate precision,
+the batched path, the adjoint, and the full-size MeerKAT-shaped workload at
+sampled bins and pixels.  Bars as for boxcar averaging: D within FP32
+rounding (2e-6), patches 1e-5 of the peak, gradients 1e-4."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import psf_synth as ps
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden")
+TOL = 1e-5
+ACCURATE = ["fp32", "split_bf16", "split_fp16"]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2009_07010_amd as pk
+    pk.lib()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def win1():
+    obs = ps.tapered_windows(ps.observation(1))
+    src = ps.sources(1)[0]
+    return obs, src, orc.decorr(obs, src.l0, src.m0)
+
+
+def _D(pk, obs, l0, m0):
+    D = pk.decorr(pk.DeviceObservation(obs), l0, m0)
+    torch.cuda.synchronize()
+    return D.cpu().numpy().astype(np.complex128)
+
+
+def test_windowed_decorr_config1(pk, win1):
+    obs, src, D = win1
+    Dg = _D(pk, obs, src.l0, src.m0)
+    print(f"windowed D config1: {np.max(np.abs(Dg - D)):.2e}", flush=True)
+    assert np.max(np.abs(Dg - D)) < 2e-6
+    assert np.max(np.abs(D - orc.decorr(ps.observation(1), src.l0, src.m0))) > 1e-3
+
+
+def test_windowed_decorr_bda_time_and_channel_windows(pk):
+    obs = ps.tapered_windows(ps.tiny_random(3, n_ant=12, n_t=120, n_ch=16, nt=12, nc=4, radius_m=4000.0,
+                                            bda=True), strength=0.9)
+    for l0, m0 in ((0.02, -0.01), (-0.05, 0.03)):
+        assert np.max(np.abs(_D(pk, obs, l0, m0) - orc.decorr(obs, l0, m0))) < 2e-6
+
+
+def test_window_of_ones_is_bitwise_boxcar(pk):
+    obs = ps.tiny_random(3, n_ant=12, n_t=120, n_ch=16, nt=12, nc=4, radius_m=4000.0, bda=True)
+    ones = ps.Observation(**{**obs.__dict__, "win_t": np.ones((obs.n_bl, obs.n_t), np.float32),
+                             "win_c": np.ones((obs.n_bl, obs.n_ch), np.float32)})
+    assert np.array_equal(_D(pk, ones, 0.02, -0.01), _D(pk, obs, 0.02, -0.01))
+
+
+def test_zero_window_bins_have_zero_D(pk):
+    obs = ps.tapered_windows(ps.tiny_random(5, n_ant=6, n_t=40, n_ch=8, nt=5, nc=3))
+    wt = obs.win_t.copy()
+    wt[2, 5:10] = 0.0                    # time bin 1 of baseline 2 (5-sample bins)
+    z = ps.Observation(**{**obs.__dict__, "win_t": wt})
+    tab = orc.bin_table(z)
+    hit = (tab.b == 2) & (tab.t0 == 5)
+    Dg = _D(pk, z, 0.03, 0.01)
+    assert hit.sum() == 3 and np.all(Dg[hit] == 0.0)
+    assert np.max(np.abs(Dg[~hit] - orc.decorr(z, 0.03, 0.01)[~hit])) < 2e-6
+
+
+@pytest.mark.parametrize("prec", ACCURATE)
+def test_windowed_patch_config1(pk, win1, prec):
+    obs, src, D = win1
+    P = orc.patch_factored(obs, src, D)
+    Pg = pk.patch(pk.DeviceObservation(obs), src, prec=prec)
+    torch.cuda.synchronize()
+    err = orc.peak_normalised_error(Pg.double().cpu().numpy(), P)[0]
+    print(f"windowed patch config1 {prec}: {err:.2e}", flush=True)
+    assert err < TOL
+
+
+def test_windowed_batched_mixed_sizes(pk):
+    obs = ps.tapered_windows(ps.tiny_random(3, n_ant=12, n_t=120, n_ch=16, nt=12, nc=4, radius_m=4000.0,
+                                            bda=True))
+    cell = 1.5 * ps.ARCSEC
+    srcs = []
+    for r, pa, n in ((0.3, 40.0, 65), (1.2, 200.0, 129), (0.8, 300.0, 257), (2.0, 10.0, 33)):
+        l0, m0 = ps.direction(r * ps.DEG, np.deg2rad(pa))
+        srcs.append(ps.Source.centred(l0, m0, n, cell))
+    parts = pk.split_patches(pk.patch_batched(pk.DeviceObservation(obs), srcs, prec="split_bf16"), srcs)
+    torch.cuda.synchronize()
+    for s, P in zip(srcs, parts):
+        err = orc.peak_normalised_error(P.double().cpu().numpy(), orc.patch_factored(obs, s))[0]
+        print(f"windowed batched {s.nl}: {err:.2e}", flush=True)
+        assert err < TOL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_windowed_backward_config1(pk, prec):
+    """dL/d(l0, m0, flux) of the patch-fitting loss with windowed D against
+    the oracle's analytic gradient (which differentiates the windowed mean)."""
+    obs = ps.tapered_windows(ps.observation(1))
+    base = ps.sources(1)[0]
+    cell = 2.0 * ps.ARCSEC
+    srcs = [ps.Source.centred(l0, m0, 65, cell)
+            for l0, m0 in ((base.l0, base.m0), (-0.4 * ps.DEG, 0.7 * ps.DEG))]
+    fluxes = [1.0, 0.3]
+    g = np.random.default_rng(9)
+    moved = [s.with_direction(s.l0 + g.normal(0, ps.ARCSEC), s.m0 + g.normal(0, ps.ARCSEC)) for s in srcs]
+    T = [(f * orc.patch_factored(obs, m)).astype(np.float32) for f, m in zip(fluxes, moved)]
+    T64 = [t.astype(np.float64) for t in T]
+    L_ref, g_ref, gf_ref = orc.loss_grad_analytic(obs, srcs, fluxes, T64)
+    P64 = [orc.patch_factored(obs, s) for s in srcs]
+    fscale = [2.0 * np.sum(np.abs((f * P - t) * P)) for f, P, t in zip(fluxes, P64, T64)]
+    dobs = pk.DeviceObservation(obs)
+    lm = torch.tensor([[s.l0, s.m0] for s in srcs], dtype=torch.float64, requires_grad=True)
+    f = torch.tensor(fluxes, dtype=torch.float32, device="cuda", requires_grad=True)
+    out = pk.psf_patch_fn().apply(lm, f, dobs, srcs, prec)
+    loss = ((out.double() - torch.as_tensor(np.stack(T), device="cuda").double()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert abs(float(loss) - L_ref) <= 1e-3 * L_ref
+    g_lm, g_f = lm.grad.numpy(), f.grad.double().cpu().numpy()
+    for s in range(len(srcs)):
+        err = np.max(np.abs(g_lm[s] - g_ref[s])) / np.max(np.abs(g_ref[s]))
+        ferr = abs(g_f[s] - gf_ref[s]) / fscale[s]
+        print(f"windowed grad {prec} src{s}: dir {err:.2e} flux {ferr:.2e}", flush=True)
+        assert err <= 1e-4 and ferr <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def win2():
+    if not os.path.exists(os.path.join(GOLD, "config2_seed0_win_pixels.npy")):
+        pytest.skip("golden values for windowed workload 2 not generated")
+    return ps.tapered_windows(ps.observation(2, seed=0)), ps.sources(2, seed=0)[0]
+
+
+def test_windowed_config2_decorr_sample(pk, win2):
+    obs, src = win2
+    meta = json.load(open(os.path.join(GOLD, "config2_seed0_win.json")))
+    assert obs.K == meta["K"]
+    smp = np.load(os.path.join(GOLD, "config2_seed0_win_Dsample.npy"))
+    ks = smp[:, 0].astype(np.int64)
+    Dg = _D(pk, obs, src.l0, src.m0)[ks]
+    assert np.max(np.abs(Dg - (smp[:, 1] + 1j * smp[:, 2]))) < 2e-6
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
+def test_windowed_config2_sampled_pixels(pk, win2, prec):
+    """Workload 2 at full size (K = 5.8e6, 257 x 257) with windows, in the
+    single-source launch the benchmark times, at sampled pixels."""
+    obs, src = win2
+    rows = np.load(os.path.join(GOLD, "config2_seed0_win_pixels.npy"))
+    P = pk.patch(pk.DeviceObservation(obs), src, prec=prec)
+    torch.cuda.synchronize()
+    got = P.double().cpu().numpy()[rows[:, 0].astype(int), rows[:, 1].astype(int)]
+    err = np.max(np.abs(got - rows[:, 2])) / abs(rows[0, 3])
+    print(f"windowed config2 {prec}: {err:.2e}", flush=True)
+    assert err <= TOL
