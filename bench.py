@@ -115,6 +115,35 @@ def time_method1(pk, torch, dobs, src, prec, ws, reps=10):
             "psf_from_sinc_ms": psf_ms}
 
 
+def time_windows_fullw(pk, torch, ps, obs, dobs, src, prec, ws, reps=5):
+    """Windowed averaging (tapered baseline-dependent windows on both axes)
+    and the exact-w patch on the same workload and source."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    dw = pk.DeviceObservation(ps.tapered_windows(obs))
+    D = torch.empty((dobs.K, 2), dtype=torch.float32, device="cuda")
+    win = {"decorr_windowed_ms": timed(lambda: pk.decorr(dw, src.l0, src.m0, out=D)),
+           "decorr_boxcar_ms": timed(lambda: pk.decorr(dobs, src.l0, src.m0, out=D)),
+           "psf_windowed_ms": timed(lambda: pk.patch(dw, src, prec=prec, workspace=ws))}
+    del dw
+    out = torch.empty((src.nl, src.nm), dtype=torch.float32, device="cuda")
+    n_terms = pk.patch_fullw(dobs, src, prec=prec, out=out, workspace=ws)[1]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pk.patch_fullw(dobs, src, prec=prec, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    fullw = {"ms": (time.perf_counter() - t0) / reps * 1e3, "contractions": n_terms}
+    return win, fullw
+
+
 def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     """Hogbom CLEAN with the distorted PSF at every peak on a 257 x 257 image
     of this workload: three sources placed on pixels, dirty image formed by
@@ -226,6 +255,7 @@ def main():
     }
     line["method1"] = time_method1(pk, torch, dobs, src, a.prec, ws)
     line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)
+    line["windows"], line["fullw"] = time_windows_fullw(pk, torch, ps, obs, dobs, src, a.prec, ws)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
     print(json.dumps(line), flush=True)

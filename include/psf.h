@@ -173,10 +173,10 @@ int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
  * in a centred Taylor series whose terms are linearised patches with
  * modified coefficients, each contracted with the arithmetic prec; the
  * order follows from the range of q over the grid and a bound of |w| (a
- * truncation bound of 1e-9 of the coefficient sum).  *n_terms (host, may be
+ * truncation bound of 1e-7 of the coefficient sum).  *n_terms (host, may be
  * NULL) receives the number of contractions.  Fails with PSF_EINVAL when a
  * grid corner lies outside the sky or the non-linear phase spans more than
- * 6 rad over the patch (a patch too wide for the expansion).  Synchronises
+ * 4 rad over the patch (a patch too wide for the expansion).  Synchronises
  * the stream once (to read the |w| bound): not capturable.  ws sized with
  * psf_workspace_bytes; P (device, float [nl][nm]) must not overlap it. */
 int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P, int32_t* n_terms,

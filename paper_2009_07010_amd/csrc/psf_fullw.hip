@@ -18,8 +18,9 @@
 // The pixel weights (delta / Y)^r lie in [-1, 1] and the coefficients
 // shrink with r, so no term leaves the FP16 range of the split-FP16 form.
 // R is the smallest order whose truncation bound Y^(R+1)/(R+1)! is at most
-// kTruncation; Y is limited to kMaxY so that the alternating terms (up to
-// e^Y of the patch) do not amplify the contraction's rounding.
+// kTruncation (1e-7 of the coefficient sum, below the contraction's own
+// rounding); Y is limited to kMaxY so that the terms (together up to e^Y of
+// the patch) do not amplify the contraction's rounding past 1e-5.
 #include <cmath>
 
 #include "psf_device.hpp"
@@ -29,8 +30,8 @@ namespace psf {
 
 namespace {
 
-constexpr double kMaxY = 3.0;
-constexpr double kTruncation = 1e-9;
+constexpr double kMaxY = 2.0;
+constexpr double kTruncation = 1e-7;
 constexpr int kMaxOrder = 40;
 
 // s = max |w_c| over the time-bin centres times the largest channel

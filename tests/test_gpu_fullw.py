@@ -77,7 +77,7 @@ def test_fullw_without_w_is_the_linearised_patch(pk, wide):
 
 
 def test_fullw_rejects_a_patch_too_wide_for_the_expansion(pk, wide):
-    src = ps.Source.centred(0.3, -0.2, 48, 40.0 * ps.ARCSEC)     # non-linear phase spans 15 rad
+    src = ps.Source.centred(0.3, -0.2, 48, 40.0 * ps.ARCSEC)     # non-linear phase spans 15 rad (limit 4)
     with pytest.raises(pk.PsfError) as e:
         pk.patch_fullw(pk.DeviceObservation(wide), src)
     assert e.value.status == pk.PSF_EINVAL
