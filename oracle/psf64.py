@@ -46,11 +46,13 @@ from __future__ import annotations
 import cmath
 import dataclasses
 import math
+import types
 
 import numpy as np
 
 C_LIGHT = 299792458.0            # m / s
 TWO_PI = 2.0 * math.pi
+OMEGA_EARTH = 7.2921150e-5       # rad / s, sidereal rotation rate
 
 
 # --------------------------------------------------------------------------
@@ -433,6 +435,62 @@ def patch_fullw_pixels(obs, src, ii, jj, D: np.ndarray = None, block: int = 1 <<
                                                            + uk[sl, 2] * N[i, j])))
         out[n] = 2.0 * acc.real
     return out
+
+
+# --------------------------------------------------------------------------
+# Method 2, the image-plane approximation [section 3.2]
+# --------------------------------------------------------------------------
+def method2_grid(N: int, cell: float):
+    """The centred N x N grid of Method 2 (N even): pixel i at offset
+    (i - N/2) cell, and its discrete uv plane: cell a at (a - N/2) du with
+    du = 1 / (N cell) [Algorithm 1, the uv cell size from the image extent]."""
+    off = (np.arange(N) - N // 2).astype(np.float64)
+    return off * cell, off / (N * cell)
+
+
+def method2_dhat(u0, v0, l0: float, m0: float, dt: float, dnu: float, nu: float):
+    """The pixelised decorrelation of Method 2 [section 3.2, the fringe-rate
+    model and Algorithm 1] at uv cells (u0, v0) in wavelengths, for a source
+    at (l0, m0), bins of dt seconds and dnu Hz at frequency nu:
+    a circular track of radius |u0| turning at omega_E has fringe rate
+    (du/dt, dv/dt) = omega_E (-v0, u0) (theta the polar angle of (u0, v0),
+    as in the track equations), so
+        dPsi = 2 pi (du/dt l0 + dv/dt m0) dt,
+        dPhi = 2 pi (dnu/nu) |l0| |u0|,
+        D^   = sinc(dPsi/2) sinc(dPhi/2),   sinc(x) = sin(x)/x.
+    Readings (the algorithm's listing is garbled): uv in wavelengths with no
+    further nu/c factor; the direction is the source's (l0, m0); cells step
+    by du, not (N-1)/N du."""
+    u0 = np.asarray(u0, np.float64)
+    v0 = np.asarray(v0, np.float64)
+    dpsi = TWO_PI * OMEGA_EARTH * (-v0 * l0 + u0 * m0) * dt
+    dphi = TWO_PI * (dnu / nu) * math.hypot(l0, m0) * np.hypot(u0, v0)
+    return np.sinc(dpsi / (2.0 * math.pi)) * np.sinc(dphi / (2.0 * math.pi))
+
+
+def method2_effective_psf(obs, N: int, cell: float) -> np.ndarray:
+    """The effective PSF [section 2.2: the PSF at the phase centre, no
+    decorrelation] on the centred N x N grid: D = 1, l0 = m0 = 0."""
+    x, _ = method2_grid(N, cell)
+    grid = types.SimpleNamespace(l0=0.0, m0=0.0, l_first=float(x[0]), m_first=float(x[0]), dl=cell, dm=cell,
+                                 nl=N, nm=N)
+    return patch_factored(obs, grid, np.ones(int(obs.bl_koff[-1]), complex))
+
+
+def method2_patch(P_eff: np.ndarray, cell: float, l0: float, m0: float, dt: float, dnu: float,
+                  nu: float) -> np.ndarray:
+    """Method 2 [section 3.2, the FFT form of the image-plane convolution]:
+    the spectrum of the effective PSF on the centred grid times the
+    pixelised D^, transformed back; real part, on the same centred grid of
+    offsets from the source.  The transforms are the periodic DFT on the
+    N x N grid: the edge row and column (offset -N/2) and the Nyquist cells
+    (frequency -N/2) are taken as the DFT has them, without symmetrising."""
+    N = P_eff.shape[0]
+    _, uu = method2_grid(N, cell)
+    U, V = np.meshgrid(uu, uu, indexing="ij")
+    S = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(P_eff)))
+    out = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(S * method2_dhat(U, V, l0, m0, dt, dnu, nu))))
+    return out.real
 
 
 def effective_psf_closed_form(obs, src) -> np.ndarray:

@@ -621,3 +621,100 @@ def test_fullw_peak_and_pixels(cfg1):
     assert abs(P[c, c] - 2.0 * np.sum(obs.W * D.real)) < 1e-9 * abs(P[c, c])
     ii, jj = np.array([0, 3, c, src.nl - 1]), np.array([5, 0, c, src.nm - 2])
     assert np.max(np.abs(orc.patch_fullw_pixels(obs, src, ii, jj) - P[ii, jj])) < 1e-9 * abs(P[c, c])
+
+
+# ---------------------------------------------------------------- Method 2
+def _one_visibility(u, v, W=1.0):
+    """One baseline, one sample, one channel at nu = c (so metres are
+    wavelengths exactly), w = 0."""
+    uvw = np.array([[[u, v, 0.0]]])
+    bl_bin = np.array([[1, 1]], np.int32)
+    koff, tboff = ps.bin_tables(1, 1, bl_bin)
+    return ps.Observation(ant_enu=np.zeros((2, 3)), bl_ant=np.array([[0, 1]], np.int32), times_s=np.zeros(1),
+                          uvw_m=uvw, freq_hz=np.array([C]), bl_bin=bl_bin, bl_koff=koff, bl_tboff=tboff,
+                          uvw_c_m=uvw[0].copy(), W=np.array([W], np.float32))
+
+
+def test_method2_at_phase_centre_is_the_effective_psf(cfg1):
+    obs, _ = cfg1
+    P = orc.method2_effective_psf(obs, 64, 4.0 * ps.ARCSEC)
+    Q = orc.method2_patch(P, 4.0 * ps.ARCSEC, 0.0, 0.0, 30.0, 2e6, 1.4e9)
+    assert np.max(np.abs(P - Q)) < 1e-12 * np.max(np.abs(P))
+    assert P[32, 32] == pytest.approx(2.0 * float(np.sum(obs.W, dtype=np.float64)), rel=1e-12)
+
+
+@pytest.mark.parametrize("a,b", [(3, -5), (0, 7), (-11, 2)])
+def test_method2_grid_aligned_visibility_is_scaled_by_dhat(a, b):
+    """A visibility on a uv cell: its effective PSF is periodic on the grid,
+    its spectrum two spikes at +-(a, b), so Method 2 returns the effective
+    PSF times D^ of that cell (which cell the spectrum lands on and how the
+    grid is centred are what this checks)."""
+    N, cell = 32, 1e-3
+    du = 1.0 / (N * cell)
+    obs = _one_visibility(a * du, b * du, W=0.7)
+    P = orc.method2_effective_psf(obs, N, cell)
+    l0, m0, dt, dnu, nu = 0.02, -0.015, 3000.0, 4e7, 1.0e9
+    Q = orc.method2_patch(P, cell, l0, m0, dt, dnu, nu)
+    d = orc.method2_dhat(a * du, b * du, l0, m0, dt, dnu, nu)
+    assert 0.01 < abs(d) < 0.999
+    assert np.max(np.abs(Q - d * P)) < 1e-12
+
+
+def test_method2_fringe_rate_matches_a_polar_circular_track():
+    """At the celestial pole a baseline's uv track is a circle turning at
+    omega_E: the model's time smearing phase equals the exact change of
+    u.l0 across a bin of dt seconds (to (omega dt)^2)."""
+    g = np.random.default_rng(3)
+    bl = g.normal(0.0, 3000.0, size=(4, 3))
+    nu, dt = 1.4e9, 20.0
+    for t in (-3000.0, 0.0, 1234.0):
+        H = ps.OMEGA_EARTH * np.array([t - dt / 2, t, t + dt / 2])
+        uvw = ps.uvw_tracks(bl, H, lat=math.radians(52.0), dec=math.radians(90.0)) * nu / C   # [bl, 3, 3]
+        for l0, m0 in ((0.03, -0.01), (-0.02, 0.05)):
+            exact = 2 * math.pi * ((uvw[:, 2, 0] - uvw[:, 0, 0]) * l0 + (uvw[:, 2, 1] - uvw[:, 0, 1]) * m0)
+            u0, v0 = uvw[:, 1, 0], uvw[:, 1, 1]
+            model = 2 * math.pi * orc.OMEGA_EARTH * (-v0 * l0 + u0 * m0) * dt
+            assert np.allclose(model, exact, rtol=1e-6, atol=0)
+            d = orc.method2_dhat(u0, v0, l0, m0, dt, 0.0, nu)
+            assert np.allclose(d, np.sinc(exact / (2 * math.pi)), rtol=0, atol=1e-6)
+
+
+def test_method2_frequency_term_is_the_band_average_along_the_baseline():
+    """For a direction along the baseline the model's bandwidth phase is the
+    exact one: D^ (no time smearing) equals the band average of the fringe
+    over dnu, by quadrature."""
+    u0, v0 = 1800.0, -2400.0                   # wavelengths at nu
+    nu, dnu = 1.4e9, 3e6
+    unit = np.array([u0, v0]) / math.hypot(u0, v0)
+    for r in (0.01, 0.04):
+        l0, m0 = r * unit
+        f = nu + dnu * ((np.arange(200000) + 0.5) / 200000 - 0.5)       # midpoint rule
+        avg = np.mean(np.exp(-2j * math.pi * (u0 * l0 + v0 * m0) * f / nu))
+        d = orc.method2_dhat(u0, v0, l0, m0, 0.0, dnu, nu)
+        assert abs(abs(avg) - d) < 1e-8
+
+
+def test_method2_on_grid_visibilities_equals_direct_sum():
+    """Several visibilities on uv cells of the grid: Method 2 equals the
+    direct sum 2 sum_k W_k D^(u_k) cos(2 pi (u_k x + v_k y)) over the patch,
+    each visibility scaled by the D^ of its own cell."""
+    N, cell = 64, 2e-4
+    du = 1.0 / (N * cell)
+    cells = [(3, -5), (0, 7), (-11, 2), (20, 13), (-7, -29)]
+    W = [0.7, 1.3, 0.4, 1.0, 0.9]
+    uvw = np.array([[[a * du, b * du, 0.0]] for a, b in cells])
+    bl_bin = np.ones((len(cells), 2), np.int32)
+    koff, tboff = ps.bin_tables(1, 1, bl_bin)
+    obs = ps.Observation(ant_enu=np.zeros((2, 3)), bl_ant=np.zeros((len(cells), 2), np.int32),
+                         times_s=np.zeros(1), uvw_m=uvw, freq_hz=np.array([C]), bl_bin=bl_bin, bl_koff=koff,
+                         bl_tboff=tboff, uvw_c_m=uvw[:, 0, :].copy(), W=np.array(W, np.float32))
+    l0, m0, dt, dnu, nu = 0.05, 0.03, 4000.0, 3e7, 1.0e9
+    Q = orc.method2_patch(orc.method2_effective_psf(obs, N, cell), cell, l0, m0, dt, dnu, nu)
+    x, _ = orc.method2_grid(N, cell)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    ref = np.zeros((N, N))
+    for (a, b), w in zip(cells, W):
+        d = orc.method2_dhat(a * du, b * du, l0, m0, dt, dnu, nu)
+        ref += 2.0 * float(np.float32(w)) * d * np.cos(2 * math.pi * (a * du * X + b * du * Y))
+    assert np.max(np.abs(Q - ref)) < 1e-11 * np.max(np.abs(ref))
+    assert np.max(np.abs(Q - orc.method2_effective_psf(obs, N, cell))) > 0.1 * np.max(np.abs(ref))
