@@ -182,6 +182,35 @@ int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
 int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P, int32_t* n_terms,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* Method 2, the image-plane approximation [section 3.2, Algorithm 1]: one
+ * decorrelation for all baselines, pixelised over the uv plane from a
+ * fringe-rate model (circular tracks turning at the sidereal rate:
+ * dPsi = 2 pi omega_E (-v0 l0 + u0 m0) dt, dPhi = 2 pi (dnu/nu) |l0| |u0|,
+ * D^ = sinc(dPsi/2) sinc(dPhi/2)), applied to the effective PSF (the PSF at
+ * the phase centre, section 2.2) as a product of Fourier transforms.
+ * Grid: N x N, N a power of two in 16..4096, square cells of `cell`
+ * radians; pixel i at offset (i - N/2) cell; uv cell a at a' / (N cell)
+ * wavelengths, a' = a for a < N/2 and a - N otherwise (DFT order).
+ *
+ * psf_method2_spectrum (once per observation and grid): the effective PSF
+ * on the centred grid (patch contraction at l0 = m0 = 0, arithmetic prec,
+ * windows honoured) and its forward 2-D DFT into S (device, float
+ * [N][N][2], DFT order).  ws sized with psf_method2_workspace_bytes.
+ *
+ * psf_method2_patch (per source): P[s] = Re DFT^-1 (S D^(l0_s, m0_s)) / N^2
+ * on the centred grid of offsets from the source (device, float
+ * [n_src][N][N]).  h_dirs: host double [n_src][2] = (l0, m0); dt_bin and
+ * dnu_bin are the averaging bin's duration (s) and bandwidth (Hz), nu the
+ * frequency (Hz) of the fractional bandwidth.  Sources are processed 16 per
+ * launch; ws holds min(n_src, 16) N^2 complex floats.  Neither call
+ * synchronises; S must stay valid until psf_method2_patch has run. */
+int psf_method2_workspace_bytes(const psf_obs* obs, int32_t N, int prec, int32_t n_src, size_t* out);
+int psf_method2_spectrum(const psf_obs* obs, int32_t N, double cell, int prec, float* S, void* ws,
+                         size_t ws_bytes, void* stream);
+int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, const double* h_dirs,
+                      double dt_bin, double dnu_bin, double nu, float* P, void* ws, size_t ws_bytes,
+                      void* stream);
+
 /* Hogbom CLEAN with position-dependent PSFs [Algorithm 2]: up to max_iter
  * minor cycles on the image `residual` (device, float [nl][nm] on the grid
  * of h_grid, whose l0, m0 are ignored; in: the dirty image, out: the

@@ -52,6 +52,13 @@ _SIGNATURES = {
                                            ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "psf_decorr": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
     "psf_decorr_sinc": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_double, ctypes.c_double, _P, _P]),
+    "psf_method2_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.c_int,
+                                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "psf_method2_spectrum": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.c_double, ctypes.c_int,
+                                            _P, _P, ctypes.c_size_t, _P]),
+    "psf_method2_patch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, _P, ctypes.c_int32, _P,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P,
+                                         ctypes.c_size_t, _P]),
     "psf_patch_fullw": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), ctypes.c_int, _P,
                                        ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
     "psf_patch": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P, _P,
@@ -290,6 +297,35 @@ def patch_fullw(dobs: DeviceObservation, src, prec="split_bf16", out=None, works
     P = torch.empty((int(src.nl), int(src.nm)), dtype=torch.float32, device=dobs.device) if out is None else out
     n = psf_patch_fullw(dobs.struct, hs, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return P, n
+
+
+def method2_spectrum(dobs: DeviceObservation, N: int, cell: float, prec="split_bf16",
+                     workspace: Optional[Workspace] = None):
+    """Method 2, once per observation and grid: the DFT of the effective PSF
+    on the centred N x N grid, complex64 [N, N] in DFT order."""
+    torch = _torch()
+    need = ctypes.c_size_t(0)
+    _check(lib().psf_method2_workspace_bytes(ctypes.byref(dobs.struct), int(N), _prec(prec), 1, ctypes.byref(need)))
+    ws = (workspace or Workspace(dobs.device)).get(need.value)
+    S = torch.empty((int(N), int(N), 2), dtype=torch.float32, device=dobs.device)
+    _check(lib().psf_method2_spectrum(ctypes.byref(dobs.struct), int(N), float(cell), _prec(prec), S.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), _stream_handle()))
+    return torch.view_as_complex(S)
+
+
+def method2_patches(S, cell: float, dirs, dt_bin: float, dnu_bin: float, nu: float, out=None,
+                    workspace: Optional[Workspace] = None):
+    """Method 2 per source: float32 [n_src, N, N] on the centred grid of
+    offsets from each source; ``dirs`` is a sequence of (l0, m0)."""
+    torch = _torch()
+    N = int(S.shape[0])
+    h = (ctypes.c_double * (2 * len(dirs)))(*[float(v) for d in dirs for v in d])
+    ws = (workspace or Workspace(S.device)).get(min(len(dirs), 16) * N * N * 8)
+    P = torch.empty((len(dirs), N, N), dtype=torch.float32, device=S.device) if out is None else out
+    Sr = torch.view_as_real(S) if S.is_complex() else S
+    _check(lib().psf_method2_patch(N, float(cell), Sr.data_ptr(), len(dirs), h, float(dt_bin), float(dnu_bin),
+                                   float(nu), P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle()))
+    return P
 
 
 def patch_backward(dobs: DeviceObservation, srcs: Sequence, G_all, prec="split_bf16",

@@ -197,3 +197,20 @@ def test_fullw_host_side_errors(L):
     st, _ = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(s), 7, FAKE, ctypes.byref(n), FAKE,
                       1 << 40, None)
     assert st == pk.PSF_EINVAL
+
+
+def test_method2_host_side_errors(L):
+    o = fake_obs()
+    out = ctypes.c_size_t(0)
+    assert L.psf_method2_workspace_bytes(ctypes.byref(o), 100, 1, 1, ctypes.byref(out)) == pk.PSF_EINVAL
+    assert L.psf_method2_workspace_bytes(ctypes.byref(o), 128, 1, 4, ctypes.byref(out)) == pk.PSF_OK
+    assert out.value >= 4 * 128 * 128 * 8
+    st, _ = status_of(L.psf_method2_spectrum, ctypes.byref(o), 128, 0.0, 1, FAKE, FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL
+    dirs = (ctypes.c_double * 4)(0.01, 0.0, 0.9, 0.9)
+    st, msg = status_of(L.psf_method2_patch, 128, 1e-5, FAKE, 2, dirs, 20.0, 1e6, 1.4e9, FAKE, FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL and "sky" in msg
+    st, _ = status_of(L.psf_method2_patch, 128, 1e-5, FAKE, 1, dirs, -1.0, 1e6, 1.4e9, FAKE, FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_method2_patch, 128, 1e-5, FAKE, 1, dirs, 20.0, 1e6, 1.4e9, FAKE, FAKE, 1024, None)
+    assert st == pk.PSF_EWORKSPACE
