@@ -144,6 +144,31 @@ def time_windows_fullw(pk, torch, ps, obs, dobs, src, prec, ws, reps=5):
     return win, fullw
 
 
+def time_method2(pk, torch, ps, dobs, src, prec, ws, N=256, n_src=16, reps=10):
+    """The paper's Method 2 on the same workload: the effective PSF and its
+    spectrum on an N x N grid at the patch's cell (once), then n_src
+    per-source patches from it (fringe-rate D^ product and inverse FFT)."""
+    cell = src.dl
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = pk.method2_spectrum(dobs, N, cell, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    spec_ms = (time.perf_counter() - t0) * 1e3
+    dirs = [(src.l0 + 1e-3 * q, src.m0 - 5e-4 * q) for q in range(n_src)]
+    out = torch.empty((n_src, N, N), dtype=torch.float32, device="cuda")
+    pk.method2_patches(S, cell, dirs, 20.0, 2.5e7, 1.4e9, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pk.method2_patches(S, cell, dirs, 20.0, 2.5e7, 1.4e9, out=out, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / reps / n_src
+    return {"grid": [N, N], "spectrum_ms": spec_ms, "per_source_ms": per, "sources_per_s": 1e3 / per,
+            "batch": n_src}
+
+
 def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     """Hogbom CLEAN with the distorted PSF at every peak on a 257 x 257 image
     of this workload: three sources placed on pixels, dirty image formed by
@@ -256,6 +281,7 @@ def main():
     line["method1"] = time_method1(pk, torch, dobs, src, a.prec, ws)
     line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)
     line["windows"], line["fullw"] = time_windows_fullw(pk, torch, ps, obs, dobs, src, a.prec, ws)
+    line["method2"] = time_method2(pk, torch, ps, dobs, src, a.prec, ws)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
     print(json.dumps(line), flush=True)
