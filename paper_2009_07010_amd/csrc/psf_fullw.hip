@@ -35,13 +35,12 @@ constexpr double kTruncation = 1e-7;
 constexpr int kMaxOrder = 40;
 
 // s = max |w_c| over the time-bin centres times the largest channel
-// frequency: an upper bound of |w_k| (wavelengths) for every bin.  One block.
-__global__ __launch_bounds__(256) void k_wmax(const double* __restrict__ uvw_c, int64_t n_tb,
-                                             const double* __restrict__ freq, int n_ch, double* __restrict__ out) {
+// frequency: an upper bound of |w_k| (wavelengths) for every bin.  Two
+// stages: kWmaxBlocks partial maxima (grid-stride), then one block.
+constexpr int kWmaxBlocks = 256;
+
+__device__ __forceinline__ void block_max2(double& w, double& f) {
   __shared__ double sw[256], sf[256];
-  double w = 0.0, f = 0.0;
-  for (int64_t t = threadIdx.x; t < n_tb; t += 256) w = fmax(w, fabs(uvw_c[3 * t + 2]));
-  for (int c = threadIdx.x; c < n_ch; c += 256) f = fmax(f, fabs(freq[c]));
   sw[threadIdx.x] = w;
   sf[threadIdx.x] = f;
   __syncthreads();
@@ -52,7 +51,34 @@ __global__ __launch_bounds__(256) void k_wmax(const double* __restrict__ uvw_c, 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sw[0] * sf[0] * kInvCLight;
+  w = sw[0];
+  f = sf[0];
+}
+
+__global__ __launch_bounds__(256) void k_wmax_partial(const double* __restrict__ uvw_c, int64_t n_tb,
+                                                     const double* __restrict__ freq, int n_ch,
+                                                     double* __restrict__ part) {
+  double w = 0.0, f = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; t < n_tb; t += stride)
+    w = fmax(w, fabs(uvw_c[3 * t + 2]));
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; c < n_ch; c += stride)
+    f = fmax(f, fabs(freq[c]));
+  block_max2(w, f);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = w;
+    part[2 * blockIdx.x + 1] = f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wmax_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double w = 0.0, f = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    w = fmax(w, part[2 * b]);
+    f = fmax(f, part[2 * b + 1]);
+  }
+  block_max2(w, f);
+  if (threadIdx.x == 0) out[0] = w * f * kInvCLight;
 }
 
 // Per bin: z_k = w_k / s and c~_k = c_k exp(i z_k ybar) (FP64 phase).
@@ -135,7 +161,7 @@ FullwLayout fullw_layout(const psf_obs* o, const psf_src* src, const PatchPlan& 
   L.cr = L.z + align_up(K * sizeof(float), 256);
   L.Pr = L.cr + align_up(K * sizeof(float2), 256);
   L.s = L.Pr + align_up(static_cast<size_t>(src->nl) * src->nm * sizeof(float), 256);
-  L.total = L.s + 256;
+  L.total = L.s + align_up((2 * kWmaxBlocks + 1) * sizeof(double), 256);
   return L;
 }
 
@@ -202,7 +228,10 @@ int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P
   if (obs->K > 0) {
     e = launch_decorr(view(obs), h_src->l0, h_src->m0, h_src->dl, h_src->dm, nullptr, nullptr, rec, c, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
-    hipLaunchKernelGGL(k_wmax, dim3(1), dim3(256), 0, s, obs->uvw_c_m, obs->n_tb, obs->freq_hz, obs->n_ch, d_s);
+    double* part = d_s + 1;
+    hipLaunchKernelGGL(k_wmax_partial, dim3(kWmaxBlocks), dim3(256), 0, s, obs->uvw_c_m, obs->n_tb, obs->freq_hz,
+                       obs->n_ch, part);
+    hipLaunchKernelGGL(k_wmax_final, dim3(1), dim3(256), 0, s, part, kWmaxBlocks, d_s);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_wmax launch");
     if ((e = hipMemcpyAsync(&smax, d_s, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)

@@ -59,13 +59,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(float2* __restrict__ 
   for (int n = threadIdx.x; n < N; n += kFftThreads) base[n * elem_stride] = lds[cur * N + n];
 }
 
-// Centred real image -> DFT order complex: buf[(i + N/2) % N][(j + N/2) % N] = P[i][j].
-__global__ __launch_bounds__(256) void k_m2_load(const float* __restrict__ P, float2* __restrict__ buf, int N) {
+// Centred real image (row pitch `pitch` >= N) -> DFT order complex:
+// buf[(i + N/2) % N][(j + N/2) % N] = P[i][j].
+__global__ __launch_bounds__(256) void k_m2_load(const float* __restrict__ P, int pitch, float2* __restrict__ buf,
+                                                 int N) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (e >= static_cast<int64_t>(N) * N) return;
   const int i = static_cast<int>(e / N), j = static_cast<int>(e - static_cast<int64_t>(i) * N);
   const int h = N >> 1, msk = N - 1;
-  buf[static_cast<int64_t>((i + h) & msk) * N + ((j + h) & msk)] = make_float2(P[e], 0.0f);
+  buf[static_cast<int64_t>((i + h) & msk) * N + ((j + h) & msk)] =
+      make_float2(P[static_cast<int64_t>(i) * pitch + j], 0.0f);
 }
 
 struct Dirs {
@@ -129,12 +132,15 @@ int fft2(float2* data, int N, int n_batch, float sign, hipStream_t s) {
   return e == hipSuccess ? PSF_OK : hip_fail(e, "k_fft_lines launch");
 }
 
+// The grid the effective PSF is contracted on: offsets -N/2 .. N/2 - 1, or
+// -N/2 .. N/2 (one more row and column, dropped when loaded) where N + 1 is
+// one of the patch sizes with a tuned tile family (65, 129, 257).
 psf_src effective_grid(int32_t N, double cell) {
   psf_src g{};
   g.l0 = g.m0 = 0.0;
   g.l_first = g.m_first = -(N / 2) * cell;
   g.dl = g.dm = cell;
-  g.nl = g.nm = N;
+  g.nl = g.nm = (N == 64 || N == 128 || N == 256) ? N + 1 : N;
   g.out_off = 0;
   return g;
 }
@@ -146,7 +152,7 @@ struct SpectrumLayout {
 SpectrumLayout spectrum_layout(const psf_obs* o, const PatchPlan& plan, int32_t N) {
   SpectrumLayout L;
   L.Peff = align_up(patch_workspace(o, plan), 256);
-  L.total = L.Peff + align_up(static_cast<size_t>(N) * N * sizeof(float), 256);
+  L.total = L.Peff + align_up(static_cast<size_t>(N + 1) * (N + 1) * sizeof(float), 256);
   return L;
 }
 
@@ -205,7 +211,7 @@ int psf_method2_spectrum(const psf_obs* obs, int32_t N, double cell, int prec, f
   if ((st = contract(obs, &g, plan, prec, rec, c, partial, Peff, s)) != PSF_OK) return st;
   const int64_t NN = static_cast<int64_t>(N) * N;
   float2* Sc = reinterpret_cast<float2*>(S);
-  hipLaunchKernelGGL(k_m2_load, dim3(static_cast<unsigned>((NN + 255) / 256)), dim3(256), 0, s, Peff, Sc, N);
+  hipLaunchKernelGGL(k_m2_load, dim3(static_cast<unsigned>((NN + 255) / 256)), dim3(256), 0, s, Peff, g.nm, Sc, N);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_m2_load launch");
   return fft2(Sc, N, 1, -1.0f, s);
 }
