@@ -63,6 +63,19 @@ def test_method2_patches_match_oracle(pk, cfg1, prec):
         assert e < TOL
 
 
+@pytest.mark.parametrize("N,cell", [(16, 30.0), (2048, 0.5)])
+def test_method2_smallest_and_large_grids(pk, N, cell):
+    obs = ps.observation(1)
+    cell *= ps.ARCSEC
+    Peff = orc.method2_effective_psf(obs, N, cell)
+    S = pk.method2_spectrum(pk.DeviceObservation(obs), N, cell)
+    P = pk.method2_patches(S, cell, [(0.01, 0.02)], DT, DNU, NU)
+    torch.cuda.synchronize()
+    e = _err(P[0].cpu().numpy(), orc.method2_patch(Peff, cell, 0.01, 0.02, DT, DNU, NU))
+    print(f"method-2 N={N}: {e:.2e}", flush=True)
+    assert e < TOL
+
+
 def test_method2_windowed_bda_observation(pk):
     obs = ps.tapered_windows(ps.tiny_random(3, n_ant=12, n_t=120, n_ch=16, nt=12, nc=4, radius_m=4000.0,
                                             bda=True))

@@ -99,6 +99,20 @@ def test_patch_sizes(n, nm):
         assert err < TOL, (prec, err)
 
 
+@pytest.mark.parametrize("n,nm", [(4096, 4096), (1, 4096), (4096, 1), (4096, 7)])
+def test_patch_maximum_sizes(n, nm):
+    """The largest patches the boundary accepts (4096 per side) and the
+    thinnest, on a small observation (K = 180)."""
+    obs = ps.tiny_random(33, n_ant=6, n_t=40, n_ch=6, nt=7, nc=4, radius_m=4000.0)
+    src = ps.Source.centred(0.012, -0.021, n, 0.5 * ps.ARCSEC, nm=nm)
+    P = orc.patch_factored(obs, src)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ("fp32", "split_bf16"):
+        err = orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0]
+        print(f"{n}x{nm} {prec}: {err:.2e}", flush=True)
+        assert err < TOL, (prec, err)
+
+
 # Worst-case error of one split-BF16 term relative to |a||b|: each operand
 # keeps hi + lo = 16 significant bits, |lo| <= 2^-8 |v|, and the dropped
 # lo*lo product and the rounding of both lo parts each contribute up to
