@@ -177,8 +177,10 @@ int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
  * NULL) receives the number of contractions.  Fails with PSF_EINVAL when a
  * grid corner lies outside the sky or the non-linear phase spans more than
  * 4 rad over the patch (a patch too wide for the expansion).  Synchronises
- * the stream once (to read the |w| bound): not capturable.  ws sized with
- * psf_workspace_bytes; P (device, float [nl][nm]) must not overlap it. */
+ * the stream once (to read the |w| bound): not capturable.  The span check
+ * needs that bound, so when it fails the factor and bound kernels have run
+ * (P is not written).  ws sized with psf_workspace_bytes; P (device, float
+ * [nl][nm]) must not overlap it. */
 int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P, int32_t* n_terms,
                     void* ws, size_t ws_bytes, void* stream);
 

@@ -20,6 +20,8 @@ namespace psf {
 // ------------------------------------------------------------------ errors
 static thread_local char g_msg[512] = "";
 
+void clear_error() { g_msg[0] = 0; }
+
 int fail(int status, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -298,7 +300,7 @@ int psf_timing_read(double* ms_total, int64_t* launches) {
 }
 
 int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int prec, size_t* out) {
-  g_msg[0] = 0;
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
@@ -318,7 +320,7 @@ int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs
 }
 
 int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream) {
-  g_msg[0] = 0;
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if (!std::isfinite(l0) || !std::isfinite(m0) || l0 * l0 + m0 * m0 >= 1.0)
@@ -332,7 +334,7 @@ int psf_decorr(const psf_obs* obs, double l0, double m0, float* D, void* stream)
 }
 
 int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* stream) {
-  g_msg[0] = 0;
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if (!std::isfinite(l0) || !std::isfinite(m0) || l0 * l0 + m0 * m0 >= 1.0)
@@ -348,7 +350,7 @@ int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* st
 
 int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec, float* P, void* ws,
               size_t ws_bytes, void* stream) {
-  g_msg[0] = 0;
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_src(h_src, 0)) != PSF_OK) return st;

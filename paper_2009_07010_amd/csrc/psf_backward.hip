@@ -95,6 +95,7 @@ using namespace psf;
 extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, const psf_src* d_srcs,
                                   const float* G_all, int prec, double* grad_lm, void* ws, size_t ws_bytes,
                                   void* stream) {
+  clear_error();
   (void)d_srcs;
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;

@@ -244,6 +244,7 @@ extern "C" {
 
 int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, const psf_src* d_srcs, int prec,
                       const char* tuning_json, float* P_all, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
   int st;
   if ((st = validate_batch(obs, n_src, h_srcs, prec)) != PSF_OK) return st;
   if (d_srcs == nullptr || P_all == nullptr) return fail(PSF_EINVAL, "d_srcs or P_all is NULL");
@@ -260,6 +261,7 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, 
 
 int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int prec, void* ws, size_t ws_bytes,
                  char* json_out, size_t json_cap, void* stream) {
+  clear_error();
   int st;
   if ((st = validate_batch(obs, n_src, h_srcs, prec)) != PSF_OK) return st;
   if (json_out == nullptr || json_cap < 64) return fail(PSF_EINVAL, "json_out missing or too small");

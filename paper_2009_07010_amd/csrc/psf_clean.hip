@@ -112,6 +112,7 @@ using namespace psf;
 extern "C" {
 
 int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int prec, size_t* out) {
+  clear_error();
   int st;
   if ((st = validate_clean(obs, h_grid, prec)) != PSF_OK) return st;
   if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
@@ -122,6 +123,7 @@ int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int pre
 int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t max_iter, double gain,
                      double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
                      int32_t* n_comp, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
   int st;
   if ((st = validate_clean(obs, h_grid, prec)) != PSF_OK) return st;
   if (residual == nullptr || n_comp == nullptr) return fail(PSF_EINVAL, "residual or n_comp is NULL");

@@ -199,6 +199,7 @@ extern "C" {
 
 int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P, int32_t* n_terms, void* ws,
                     size_t ws_bytes, void* stream) {
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_src(h_src, 0)) != PSF_OK) return st;

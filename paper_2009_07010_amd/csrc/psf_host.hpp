@@ -22,6 +22,8 @@ struct PatchPlan {
 };
 
 int fail(int status, const char* fmt, ...);
+// Clears the thread's last-error message (every entry point starts with it).
+void clear_error();
 int hip_fail(hipError_t e, const char* what);
 int check_device();
 int validate_obs(const psf_obs* o);

@@ -169,6 +169,7 @@ using namespace psf;
 extern "C" {
 
 int psf_method2_workspace_bytes(const psf_obs* obs, int32_t N, int prec, int32_t n_src, size_t* out) {
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
@@ -183,6 +184,7 @@ int psf_method2_workspace_bytes(const psf_obs* obs, int32_t N, int prec, int32_t
 
 int psf_method2_spectrum(const psf_obs* obs, int32_t N, double cell, int prec, float* S, void* ws, size_t ws_bytes,
                          void* stream) {
+  clear_error();
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
@@ -218,6 +220,7 @@ int psf_method2_spectrum(const psf_obs* obs, int32_t N, double cell, int prec, f
 
 int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, const double* h_dirs, double dt_bin,
                       double dnu_bin, double nu, float* P, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
   int st;
   if ((st = validate_grid(N, cell)) != PSF_OK) return st;
   if (S == nullptr || P == nullptr) return fail(PSF_EINVAL, "S or P is NULL");

@@ -214,3 +214,12 @@ def test_method2_host_side_errors(L):
     assert st == pk.PSF_EINVAL
     st, _ = status_of(L.psf_method2_patch, 128, 1e-5, FAKE, 1, dirs, 20.0, 1e6, 1.4e9, FAKE, FAKE, 1024, None)
     assert st == pk.PSF_EWORKSPACE
+
+
+def test_successful_call_clears_last_error(L):
+    o = fake_obs()
+    out = ctypes.c_size_t(0)
+    assert L.psf_method2_workspace_bytes(ctypes.byref(o), 100, 1, 1, ctypes.byref(out)) == pk.PSF_EINVAL
+    assert L.psf_last_error()
+    assert L.psf_method2_workspace_bytes(ctypes.byref(o), 128, 1, 1, ctypes.byref(out)) == pk.PSF_OK
+    assert L.psf_last_error() == b""
