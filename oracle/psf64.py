@@ -163,6 +163,12 @@ def _normalise(acc: np.ndarray, wsum: np.ndarray) -> np.ndarray:
     return out
 
 
+def _bin_sum(kidx: np.ndarray, vals: np.ndarray, k0: int, k1: int) -> np.ndarray:
+    """Sum of vals per bin over one baseline's bins [k0, k1) (samples in
+    their natural order, as np.bincount adds them)."""
+    return np.bincount(kidx.ravel() - k0, vals.ravel(), minlength=k1 - k0)
+
+
 def decorr(obs, l0: float, m0: float, sign: float = -1.0) -> np.ndarray:
     """D_k, complex128 [K]: mean over each bin's samples of exp(sign 2 pi i phi_s).
 
@@ -185,18 +191,20 @@ def decorr(obs, l0: float, m0: float, sign: float = -1.0) -> np.ndarray:
     if _windowed(obs):
         wsum = np.zeros(K)
         for b in range(obs.uvw_m.shape[0]):
+            k0, k1 = int(obs.bl_koff[b]), int(obs.bl_koff[b + 1])
             phi, _, kidx = _per_baseline_phases(obs, tab, uk, b, L)
             x = sample_window(obs, b)
             e = x * np.exp(sign * 1j * TWO_PI * phi)
-            re += np.bincount(kidx.ravel(), e.real.ravel(), minlength=K)
-            im += np.bincount(kidx.ravel(), e.imag.ravel(), minlength=K)
-            wsum += np.bincount(kidx.ravel(), x.ravel(), minlength=K)
+            re[k0:k1] += _bin_sum(kidx, e.real, k0, k1)
+            im[k0:k1] += _bin_sum(kidx, e.imag, k0, k1)
+            wsum[k0:k1] += _bin_sum(kidx, x, k0, k1)
         return _normalise(re + 1j * im, wsum)
     for b in range(obs.uvw_m.shape[0]):
+        k0, k1 = int(obs.bl_koff[b]), int(obs.bl_koff[b + 1])
         phi, _, kidx = _per_baseline_phases(obs, tab, uk, b, L)
         e = np.exp(sign * 1j * TWO_PI * phi)
-        re += np.bincount(kidx.ravel(), e.real.ravel(), minlength=K)
-        im += np.bincount(kidx.ravel(), e.imag.ravel(), minlength=K)
+        re[k0:k1] += _bin_sum(kidx, e.real, k0, k1)
+        im[k0:k1] += _bin_sum(kidx, e.imag, k0, k1)
     return (re + 1j * im) / tab.n
 
 
@@ -258,17 +266,17 @@ def decorr_with_grad(obs, l0: float, m0: float):
     win = _windowed(obs)
     wsum = np.zeros(K)
     for b in range(obs.uvw_m.shape[0]):
+        k0, k1 = int(obs.bl_koff[b]), int(obs.bl_koff[b + 1])
         phi, du, kidx = _per_baseline_phases(obs, tab, uk, b, L)
         e = np.exp(-1j * TWO_PI * phi)
         if win:
             x = sample_window(obs, b)
             e = x * e
-            wsum += np.bincount(kidx.ravel(), x.ravel(), minlength=K)
+            wsum[k0:k1] += _bin_sum(kidx, x, k0, k1)
         dphi_l = du[..., 0] - du[..., 2] * l0 / n0
         dphi_m = du[..., 1] - du[..., 2] * m0 / n0
         for r, val in enumerate((e, -1j * TWO_PI * dphi_l * e, -1j * TWO_PI * dphi_m * e)):
-            acc[r] += (np.bincount(kidx.ravel(), val.real.ravel(), minlength=K)
-                       + 1j * np.bincount(kidx.ravel(), val.imag.ravel(), minlength=K))
+            acc[r, k0:k1] += _bin_sum(kidx, val.real, k0, k1) + 1j * _bin_sum(kidx, val.imag, k0, k1)
     if win:
         acc = _normalise(acc, wsum)
     else:
