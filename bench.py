@@ -169,6 +169,30 @@ def time_method2(pk, torch, ps, dobs, src, prec, ws, N=256, n_src=16, reps=10):
             "batch": n_src}
 
 
+def time_adjoint(pk, torch, ps, dobs, prec, ws, reps=3):
+    """The differentiation workload on the same data: 16 sources at 0.2-2 deg
+    with 129 x 129 patches, one batched forward and one adjoint call
+    (d/d(l0, m0) of every source from a cotangent of all 16 patches)."""
+    srcs = ps.sources(3, seed=0)
+    n = sum(s.nl * s.nm for s in srcs)
+    G = torch.randn(n, dtype=torch.float32, device="cuda")
+    pk.patch_batched(dobs, srcs, prec=prec, workspace=ws)
+    pk.patch_backward(dobs, srcs, G, prec, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pk.patch_batched(dobs, srcs, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        pk.patch_backward(dobs, srcs, G, prec, workspace=ws)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = (t1 - t0) / reps * 1e3, (t2 - t1) / reps * 1e3
+    return {"sources": len(srcs), "patch": [srcs[0].nl, srcs[0].nm], "forward_ms": fwd, "backward_ms": bwd,
+            "backward_over_forward": bwd / fwd}
+
+
 def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     """Hogbom CLEAN with the distorted PSF at every peak on a 257 x 257 image
     of this workload: three sources placed on pixels, dirty image formed by
@@ -282,6 +306,7 @@ def main():
     line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)
     line["windows"], line["fullw"] = time_windows_fullw(pk, torch, ps, obs, dobs, src, a.prec, ws)
     line["method2"] = time_method2(pk, torch, ps, dobs, src, a.prec, ws)
+    line["adjoint"] = time_adjoint(pk, torch, ps, dobs, a.prec, ws)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
     print(json.dumps(line), flush=True)

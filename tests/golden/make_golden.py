@@ -136,6 +136,29 @@ def config5():
                "columns: source index, i, j, P_ij, peak 2 Re sum W D")
 
 
+CONFIG4_SOURCES = [5, 7, 0, 2]    # radii 0.45, 1.67, 1.87, 2.8 deg
+
+
+def config4():
+    """The precision workload (K = 23.2M, 257 x 257 patches): FP64 values at
+    20 sampled pixels of four of its 64 sources, with each patch's peak."""
+    obs = ps.observation(4, seed=0)
+    srcs = ps.sources(4, seed=0)
+    pix = config5_pixels([srcs[i] for i in CONFIG4_SOURCES], 20)
+    t = time.time()
+    rows = []
+    for i, ij in zip(CONFIG4_SOURCES, pix):
+        D = orc.decorr(obs, srcs[i].l0, srcs[i].m0)
+        P = orc.patch_pixels(obs, srcs[i], ij[:, 0], ij[:, 1], D)
+        peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+        rows += [(i, a, b, v, peak) for (a, b), v in zip(ij, P)]
+        print("config4 source", i, time.time() - t, flush=True)
+    np.save(os.path.join(HERE, "config4_seed0_pixels.npy"), np.array(rows, dtype=np.float64))
+    _meta("config4_seed0", config=4, seed=0, K=obs.K, sources=CONFIG4_SOURCES, seconds=time.time() - t,
+          what="oracle.patch_pixels (FP64) at sampled pixels of four sources of workload 4; "
+               "columns: source index, i, j, P_ij, peak 2 Re sum W D")
+
+
 def config2_windows():
     """Workload 2 with the tapered baseline-dependent windows of
     ``psf_synth.tapered_windows`` (strength 1): sampled D and sampled pixels
