@@ -90,10 +90,20 @@ int parse_tuning(const char* json, std::vector<Tuning>* out) {
   return PSF_OK;
 }
 
+// Work items per CU when the caller gives no table: what the tuner picks on
+// the MeerKAT-shaped data (one for the 257- and 129-pixel families, whose
+// items are large; three for the 65-pixel family), two otherwise.
+int default_items_per_cu(const Family& f) {
+  if (f == Family{9, 8, 17, 17} || f == Family{9, 9, 9, 9}) return 1;
+  if (f == Family{5, 5, 5, 5}) return 3;
+  return kDefaultItemsPerCU;
+}
+constexpr int kMaxDefaultItemsPerCU = 3;
+
 Tuning tuning_for(const std::vector<Tuning>& table, const Family& f) {
   for (const Tuning& t : table)
     if (t.fam == f) return t;
-  return {f, kDefaultItemsPerCU, kFlushChunks};
+  return {f, default_items_per_cu(f), kFlushChunks};
 }
 
 // Group boundaries: sources ordered by family (stable), then cut into groups
@@ -250,7 +260,7 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, 
   if (d_srcs == nullptr || P_all == nullptr) return fail(PSF_EINVAL, "d_srcs or P_all is NULL");
   std::vector<Tuning> table;
   if ((st = parse_tuning(tuning_json, &table)) != PSF_OK) return st;
-  int mx = kDefaultItemsPerCU;
+  int mx = kMaxDefaultItemsPerCU;
   for (const Tuning& t : table) mx = std::max(mx, t.items_per_cu);
   const size_t need = batch_workspace_for(obs, n_src, h_srcs, prec, mx);
   if (ws == nullptr || ws_bytes < need)
