@@ -1,0 +1,334 @@
+// Reverse-mode adjoint of the patch for patches of up to 144 x 256 pixels in
+// the split-BF16 and split-FP16 forms.  The derivatives are those of the
+// five-patch form in psf_backward.hip (derivation in k_decorr.hip),
+// regrouped per visibility:
+//   dL/dl0 = 2 Re sum_k [e0_k H_k + e2_k Hx_k + e3_k Hy_k]
+//   dL/dm0 = 2 Re sum_k [e1_k H_k + e3_k Hx_k + e4_k Hy_k]
+// with H_k = sum_ij G_ij a_ki b_kj, Hx_k = sum_ij x_i G_ij a_ki b_kj and
+// Hy_k = sum_ij y_j G_ij a_ki b_kj (G = dL/dP, a and b the phase factors of
+// the forward patch).  Per visibility this needs the column T = G b_k and
+// Ty = G (y o b_k) (matrix-core products, G resident in LDS) and three dot
+// products with a_k (vector registers): two products of the patch's size per
+// visibility instead of five derivative patches.
+//
+// Layout: one workgroup of four waves (one per SIMD) per k-slice; G, scaled
+// by a power of two (FP16 range) and split hi + lo, sits in LDS as 16x32
+// operand fragments [row block][k-step][hi/lo][lane][8 values].  A wave takes
+// 16 visibilities at a time; lane l owns visibility l mod 16 and generates
+// the 8 consecutive columns 32 s + 8 (l / 16) .. + 7 of its b for k-step s
+// (the operand layout of the 16x16x32 instructions), and after the products
+// holds T at rows 16 r + 4 (l / 16) + e, e = 0..3, of the same visibility.
+#include <algorithm>
+#include <cmath>
+
+#include "psf_device.hpp"
+#include "psf_host.hpp"
+
+namespace psf {
+
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) uint8_t lds_b;
+typedef __attribute__((address_space(3))) v4u lds_v4u;
+
+constexpr int kAdjThreads = 256;  // four waves, one per SIMD
+constexpr int kAdjMaxRB = 9;      // row blocks of 16: nl <= 144
+constexpr int kAdjMaxKS = 8;      // k-steps of 32 columns: nm <= 256
+constexpr int kAdjWG = 512;       // workgroups (k-slices) per source
+constexpr int kFragBytes = 1024;  // one 16x32 16-bit operand fragment
+
+struct AdjArgs {
+  const BinRec* rec;
+  const float2* coef;  // e0..e4, vector q at coef + q K
+  const float* G;      // [nl][nm]
+  double* partial;     // [kAdjWG][2]
+  int64_t K, slice;
+  double l_first, m_first, dl, dm, l0, m0;
+  double y_scale;      // power of two: |y_j| y_scale < 1 in the y-weighted operand
+  int nl, nm, nks;
+};
+
+template <int PREC>
+__device__ __forceinline__ v4f mma(const v4u& a, const v4u& b, v4f c) {
+  if constexpr (PREC == kSplitFP16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                   0);
+}
+
+// Two values into packed 16-bit hi and lo parts (lo = v - hi, exact in FP32).
+template <int PREC>
+__device__ __forceinline__ void split2(float p, float q, uint32_t& hi, uint32_t& lo) {
+  if constexpr (PREC == kSplitFP16) {
+    hi = pack_f16x2(p, q);
+    lo = pack_f16x2(p - f16_lo_to_f32(hi), q - f16_hi_to_f32(hi));
+  } else {
+    hi = pack_bf16x2(p, q);
+    lo = pack_bf16x2(p - bf16_lo_to_f32(hi), q - bf16_hi_to_f32(hi));
+  }
+}
+
+__device__ __forceinline__ int frag_off(int rb, int ks, int part) {
+  return ((rb * kAdjMaxKS + ks) * 2 + part) * kFragBytes;
+}
+
+template <int PREC, int NRB>
+__global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds_raw[NRB * kAdjMaxKS * 2 * kFragBytes];
+  __shared__ float s_red[kAdjThreads / 64];
+  __shared__ double s_g[2][kAdjThreads / 64];
+  lds_b* lds = (lds_b*)lds_raw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // G's scale: a power of two with max |G| scale < 2^14 (FP16); 1 for BF16.
+  float g_scale = 1.0f;
+  if constexpr (PREC == kSplitFP16) {
+    float mx = 0.0f;
+    for (int p = threadIdx.x; p < a.nl * a.nm; p += kAdjThreads) mx = fmaxf(mx, fabsf(a.G[p]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) s_red[wave] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+    if (mx > 0.0f) {
+      int e;
+      frexpf(mx, &e);  // mx < 2^e
+      g_scale = ldexpf(1.0f, 14 - e);
+    }
+  }
+  // G into LDS as split operand fragments; rows >= nl and columns >= nm are 0.
+  const int n_items = NRB * a.nks * 64;
+  for (int it = threadIdx.x; it < n_items; it += kAdjThreads) {
+    const int l = it & 63, f = it >> 6;
+    const int rb = f / a.nks, ks = f - rb * a.nks;
+    const int i = 16 * rb + (l & 15), j0 = 32 * ks + 8 * (l >> 4);
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int j = j0 + t;
+      v[t] = (i < a.nl && j < a.nm) ? a.G[static_cast<int64_t>(i) * a.nm + j] * g_scale : 0.0f;
+    }
+    v4u hi, lo;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint32_t h, w;
+      split2<PREC>(v[2 * t], v[2 * t + 1], h, w);
+      hi[t] = h;
+      lo[t] = w;
+    }
+    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, 0) + l * 16) = hi;
+    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, 1) + l * 16) = lo;
+  }
+  __syncthreads();
+
+  const int n = lane & 15, jg = lane >> 4;
+  const int64_t kb = static_cast<int64_t>(blockIdx.x) * a.slice;
+  const int64_t ke = min(a.K, kb + a.slice);
+  const float inv_y = static_cast<float>(1.0 / a.y_scale);
+  const double y_lane = (a.m_first + (8 * jg) * a.dm) - a.m0;  // column 8 jg
+  const double x_lane = (a.l_first + (4 * jg) * a.dl) - a.l0;  // row 4 jg
+  const float ys0 = static_cast<float>(y_lane * a.y_scale), ystep = static_cast<float>(a.dm * a.y_scale);
+  const float xs0 = static_cast<float>(x_lane), xstep = static_cast<float>(a.dl);
+  double gl = 0.0, gm = 0.0;
+  for (int64_t k0 = kb + 16 * wave; k0 < ke; k0 += 16 * (kAdjThreads / 64)) {
+    const int64_t kk = k0 + n;
+    const bool ok = kk < ke;
+    const BinRec* r = a.rec + (ok ? kk : ke - 1);
+    const double up = r->up, vp = r->vp;
+    cf32 zb = expi_turns(vp * y_lane);
+    const cf32 s1 = expi_turns(vp * a.dm), s25 = expi_turns(vp * (25.0 * a.dm));
+    v4f acc[NRB][4];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[rb][q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < a.nks; ++ks) {
+      // b and y b at columns 32 ks + 8 jg + t, t = 0..7: re, im, y re, y im
+      v4u bh[4], bl[4];
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        const cf32 z0 = zb;
+        zb = cmul(zb, s1);
+        const cf32 z1 = zb;
+        if (t < 6) zb = cmul(zb, s1);
+        const float y0 = ys0 + static_cast<float>(32 * ks + t) * ystep, y1 = y0 + ystep;
+        uint32_t h, w;
+        split2<PREC>(z0.re, z1.re, h, w);
+        bh[0][t / 2] = h;
+        bl[0][t / 2] = w;
+        split2<PREC>(z0.im, z1.im, h, w);
+        bh[1][t / 2] = h;
+        bl[1][t / 2] = w;
+        split2<PREC>(y0 * z0.re, y1 * z1.re, h, w);
+        bh[2][t / 2] = h;
+        bl[2][t / 2] = w;
+        split2<PREC>(y0 * z0.im, y1 * z1.im, h, w);
+        bh[3][t / 2] = h;
+        bl[3][t / 2] = w;
+      }
+      zb = cmul(zb, s25);  // column 32 ks + 8 jg + 7 -> 32 (ks + 1) + 8 jg
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        const v4u gh = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, 0) + lane * 16);
+        const v4u gw = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, 1) + lane * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[rb][q] = mma<PREC>(gh, bh[q], acc[rb][q]);
+          acc[rb][q] = mma<PREC>(gh, bl[q], acc[rb][q]);
+          acc[rb][q] = mma<PREC>(gw, bh[q], acc[rb][q]);
+        }
+      }
+    }
+    // H, Hx, Hy over this lane's rows 16 rb + 4 jg + e
+    cf32 za = expi_turns(up * x_lane);
+    const cf32 t1 = expi_turns(up * a.dl), t13 = expi_turns(up * (13.0 * a.dl));
+    float h1r = 0.f, h1i = 0.f, hxr = 0.f, hxi = 0.f, hyr = 0.f, hyi = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = xs0 + static_cast<float>(16 * rb + e) * xstep;
+        const float tr = acc[rb][0][e], ti = acc[rb][1][e];
+        const float ar = za.re * tr - za.im * ti, ai = za.re * ti + za.im * tr;
+        h1r += ar;
+        h1i += ai;
+        hxr += x * ar;
+        hxi += x * ai;
+        const float ur = acc[rb][2][e], ui = acc[rb][3][e];
+        hyr += za.re * ur - za.im * ui;
+        hyi += za.re * ui + za.im * ur;
+        za = cmul(za, e < 3 ? t1 : t13);
+      }
+    }
+    // the four lane groups of a visibility hold disjoint rows
+    for (int o = 16; o <= 32; o <<= 1) {
+      h1r += __shfl_xor(h1r, o);
+      h1i += __shfl_xor(h1i, o);
+      hxr += __shfl_xor(hxr, o);
+      hxi += __shfl_xor(hxi, o);
+      hyr += __shfl_xor(hyr, o);
+      hyi += __shfl_xor(hyi, o);
+    }
+    if (jg == 0 && ok) {
+      hyr *= inv_y;
+      hyi *= inv_y;
+      const float2 e0 = a.coef[kk], e1 = a.coef[a.K + kk], e2 = a.coef[2 * a.K + kk];
+      const float2 e3 = a.coef[3 * a.K + kk], e4 = a.coef[4 * a.K + kk];
+      auto re = [](float2 c, float hr, float hi) {
+        return static_cast<double>(c.x) * hr - static_cast<double>(c.y) * hi;
+      };
+      gl += 2.0 * (re(e0, h1r, h1i) + re(e2, hxr, hxi) + re(e3, hyr, hyi));
+      gm += 2.0 * (re(e1, h1r, h1i) + re(e3, hxr, hxi) + re(e4, hyr, hyi));
+    }
+  }
+  // fixed-order workgroup sum
+  for (int o = 32; o > 0; o >>= 1) {
+    gl += __shfl_xor(gl, o);
+    gm += __shfl_xor(gm, o);
+  }
+  if (lane == 0) {
+    s_g[0][wave] = gl;
+    s_g[1][wave] = gm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sl = 0.0, sm = 0.0;
+    for (int w = 0; w < kAdjThreads / 64; ++w) {
+      sl += s_g[0][w];
+      sm += s_g[1][w];
+    }
+    a.partial[2 * blockIdx.x] = sl / g_scale;
+    a.partial[2 * blockIdx.x + 1] = sm / g_scale;
+  }
+}
+
+// grad = (sum of the workgroup partials in order) / kAdjointScale
+__global__ __launch_bounds__(256) void k_adjoint_sum(const double* __restrict__ partial, int n,
+                                                     double* __restrict__ grad) {
+  __shared__ double s[2][256];
+  double gl = 0.0, gm = 0.0;
+  for (int w = threadIdx.x; w < n; w += 256) {
+    gl += partial[2 * w];
+    gm += partial[2 * w + 1];
+  }
+  s[0][threadIdx.x] = gl;
+  s[1][threadIdx.x] = gm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (static_cast<int>(threadIdx.x) < o) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + o];
+      s[1][threadIdx.x] += s[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    grad[0] = s[0][0] / kAdjointScale;
+    grad[1] = s[1][0] / kAdjointScale;
+  }
+}
+
+template <int PREC>
+hipError_t launch_rb(int nrb, const AdjArgs& a, int n_wg, hipStream_t st) {
+  const dim3 g(n_wg), b(kAdjThreads);
+  switch (nrb) {
+    case 1: hipLaunchKernelGGL((k_adjoint<PREC, 1>), g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_adjoint<PREC, 2>), g, b, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_adjoint<PREC, 3>), g, b, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_adjoint<PREC, 4>), g, b, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_adjoint<PREC, 5>), g, b, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_adjoint<PREC, 6>), g, b, 0, st, a); break;
+    case 7: hipLaunchKernelGGL((k_adjoint<PREC, 7>), g, b, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_adjoint<PREC, 8>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_adjoint<PREC, 9>), g, b, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool adjoint_reverse_ok(int prec, const psf_obs* o, const psf_src& s) {
+  return (prec == kSplitBF16 || prec == kSplitFP16) && o->K > 0 && s.nl <= 16 * kAdjMaxRB &&
+         s.nm <= 32 * kAdjMaxKS;
+}
+
+size_t adjoint_reverse_partial_bytes() { return static_cast<size_t>(kAdjWG) * 2 * sizeof(double); }
+
+hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, const BinRec* rec,
+                                  const float2* coef, const float* G, double* partial, double* grad,
+                                  hipStream_t st) {
+  AdjArgs a;
+  a.rec = rec;
+  a.coef = coef;
+  a.G = G;
+  a.partial = partial;
+  a.K = o->K;
+  const int64_t per = (o->K + kAdjWG - 1) / kAdjWG;
+  a.slice = std::max<int64_t>(64, (per + 63) / 64 * 64);
+  const int n_wg = static_cast<int>(std::min<int64_t>(kAdjWG, (o->K + a.slice - 1) / a.slice));
+  a.l_first = s.l_first;
+  a.m_first = s.m_first;
+  a.dl = s.dl;
+  a.dm = s.dm;
+  a.l0 = s.l0;
+  a.m0 = s.m0;
+  // y offsets of the grid: |y_j| < 2^e for all j, so y 2^-e lies in (-1, 1)
+  const double ya = std::fabs(s.m_first - s.m0), yb = std::fabs(s.m_first + (s.nm - 1) * s.dm - s.m0);
+  const double ymax = std::max(ya, yb);
+  int e = 0;
+  if (ymax > 0.0) std::frexp(ymax, &e);
+  a.y_scale = std::ldexp(1.0, -e);
+  a.nl = s.nl;
+  a.nm = s.nm;
+  a.nks = (s.nm + 31) / 32;
+  const int nrb = (s.nl + 15) / 16;
+  hipError_t err = prec == kSplitFP16 ? launch_rb<kSplitFP16>(nrb, a, n_wg, st) : launch_rb<kSplitBF16>(nrb, a, n_wg, st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, st, partial, n_wg, grad);
+  return hipGetLastError();
+}
+
+}  // namespace psf

@@ -8,7 +8,10 @@
 // Each Q[e] runs through the same phase-factor generation and matrix-core
 // contraction as the forward patch; k_grad_reduce forms the two sums in
 // FP64 with a fixed reduction order.  The e vectors arrive scaled by
-// kAdjointScale, which the reduction divides out.
+// kAdjointScale, which the reduction divides out.  Patches of up to
+// 144 x 256 pixels in the split forms take the reverse-mode kernel of
+// k_adjoint.hip instead (the same sums regrouped per visibility: two
+// products of the patch's size per visibility rather than five patches).
 #include <algorithm>
 
 #include "psf_host.hpp"
@@ -64,7 +67,7 @@ hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, d
 
 namespace {
 struct BackwardLayout {
-  size_t rec, coef, partial, pe, total;
+  size_t rec, coef, partial, pe, adj, total;
 };
 
 BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
@@ -79,7 +82,8 @@ BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_src
   L.coef = L.rec + align_up(K * sizeof(BinRec), 256);
   L.partial = L.coef + align_up(5 * K * sizeof(float2), 256);
   L.pe = L.partial + align_up(partial * sizeof(float), 256);
-  L.total = L.pe + align_up(5 * pix * sizeof(float), 256);
+  L.adj = L.pe + align_up(5 * pix * sizeof(float), 256);
+  L.total = L.adj + align_up(adjoint_reverse_partial_bytes(), 256);
   return L;
 }
 }  // namespace
@@ -114,6 +118,7 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
   float2* coef = reinterpret_cast<float2*>(w + L.coef);
   float* partial = reinterpret_cast<float*>(w + L.partial);
   float* pe = reinterpret_cast<float*>(w + L.pe);
+  double* adj = reinterpret_cast<double*>(w + L.adj);
   const int64_t K = obs->K;
   for (int n = 0; n < n_src; ++n) {
     const psf_src& src = h_srcs[n];
@@ -122,6 +127,11 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
     if (K > 0) {
       e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, nullptr, coef, s);
       if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
+    }
+    if (adjoint_reverse_ok(prec, obs, src)) {
+      e = launch_adjoint_reverse(obs, src, prec, rec, coef, G_all + src.out_off, adj, grad_lm + 2 * n, s);
+      if (e != hipSuccess) return hip_fail(e, "k_adjoint launch");
+      continue;
     }
     const PatchPlan plan = plan_patch(obs, &src, prec, kTargetWorkgroups);
     for (int q = 0; q < 5; ++q)

@@ -52,6 +52,14 @@ int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s);
 size_t batched_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
 size_t fullw_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec);
+// Reverse-mode adjoint (k_adjoint.hip): whether it serves this source and
+// precision, the bytes of its per-workgroup partial sums, and the launch
+// (workgroup partials, then their fixed-order sum into grad[0..1]).
+bool adjoint_reverse_ok(int prec, const psf_obs* o, const psf_src& s);
+size_t adjoint_reverse_partial_bytes();
+hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, const BinRec* rec,
+                                  const float2* coef, const float* G, double* partial, double* grad,
+                                  hipStream_t st);
 
 bool timing_on();
 hipError_t timed_launch_begin(hipStream_t s, hipEvent_t* ev0);
