@@ -155,9 +155,12 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
  * definition [section 2.3, distorted-PSF equation] runs through D_k (its
  * derivative over the bin's samples [section 2.3 averaging]), the
  * linearised w-shift u'(l0, m0), v'(l0, m0) and the pixel offsets
- * x_i = l_i - l0, y_j = m_j - m0.  Per source it forms five derivative
- * patches with the forward contraction (arithmetic chosen by prec) and
- * reduces them against G in FP64 in a fixed order (deterministic).
+ * x_i = l_i - l0, y_j = m_j - m0.  For split-BF16 and split-FP16 patches
+ * of up to 144 x 256 pixels it evaluates the sums per visibility in reverse
+ * mode (G b and G (y b) on the matrix cores, G held on chip); otherwise it
+ * forms five derivative patches with the forward contraction (arithmetic
+ * chosen by prec) and reduces them against G.  Both accumulate in FP64 in a
+ * fixed order (deterministic).
  * h_srcs (host) gives directions, grids and out_off; d_srcs is not read
  * (may be NULL).  G_all must hold every source's block: the library cannot
  * check device extents. */
