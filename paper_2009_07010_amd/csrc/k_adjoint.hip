@@ -1,5 +1,6 @@
-// Reverse-mode adjoint of the patch for patches of up to 144 x 256 pixels in
-// the split-BF16 and split-FP16 forms.  The derivatives are those of the
+// Reverse-mode adjoint of the patch for patches of up to 288 columns (and
+// rows within 16 ranges that fit in LDS) in the split-BF16 and split-FP16
+// forms.  The derivatives are those of the
 // five-patch form in psf_backward.hip (derivation in k_decorr.hip),
 // regrouped per visibility:
 //   dL/dl0 = 2 Re sum_k [e0_k H_k + e2_k Hx_k + e3_k Hy_k]
@@ -11,9 +12,11 @@
 // products with a_k (vector registers): two products of the patch's size per
 // visibility instead of five derivative patches.
 //
-// Layout: one workgroup of four waves (one per SIMD) per k-slice; G, scaled
-// by a power of two (FP16 range) and split hi + lo, sits in LDS as 16x32
-// operand fragments [row block][k-step][hi/lo][lane][8 values].  A wave takes
+// Layout: one workgroup of four waves (one per SIMD) per (k-slice, range of
+// row blocks whose G fragments fit in LDS): H is a sum over rows, so the row
+// ranges' shares of the gradient add.  G's rows of the range, scaled by a power of two (FP16
+// range) and split hi + lo, sit in LDS as 16x32 operand fragments
+// [row block][k-step][hi/lo][lane][8 values].  A wave takes
 // 16 visibilities at a time; lane l owns visibility l mod 16 and generates
 // the 8 consecutive columns 32 s + 8 (l / 16) .. + 7 of its b for k-step s
 // (the operand layout of the 16x16x32 instructions), and after the products
@@ -36,17 +39,20 @@ typedef __attribute__((address_space(3))) uint8_t lds_b;
 typedef __attribute__((address_space(3))) v4u lds_v4u;
 
 constexpr int kAdjThreads = 256;  // four waves, one per SIMD
-constexpr int kAdjMaxRB = 9;      // row blocks of 16: nl <= 144
-constexpr int kAdjMaxKS = 8;      // k-steps of 32 columns: nm <= 256
-constexpr int kAdjWG = 512;       // workgroups (k-slices) per source
+constexpr int kAdjMaxRB = 9;      // row blocks of 16 per workgroup
+constexpr int kAdjMaxKS = 9;      // k-steps of 32 columns: nm <= 288
+constexpr int kAdjMaxFrags = 72;  // G fragment pairs in LDS (144 KiB)
+constexpr int kAdjMaxRanges = 16; // row ranges per patch
+constexpr int kAdjSlices = 512;   // k-slices per source
 constexpr int kFragBytes = 1024;  // one 16x32 16-bit operand fragment
 
 struct AdjArgs {
   const BinRec* rec;
   const float2* coef;  // e0..e4, vector q at coef + q K
   const float* G;      // [nl][nm]
-  double* partial;     // [kAdjWG][2]
+  double* partial;     // [ranges][slices][2]
   int64_t K, slice;
+  int rb_per_range;    // row blocks per range (the last range may have fewer)
   double l_first, m_first, dl, dm, l0, m0;
   double y_scale;      // power of two: |y_j| y_scale < 1 in the y-weighted operand
   int nl, nm, nks;
@@ -73,17 +79,22 @@ __device__ __forceinline__ void split2(float p, float q, uint32_t& hi, uint32_t&
   }
 }
 
-__device__ __forceinline__ int frag_off(int rb, int ks, int part) {
-  return ((rb * kAdjMaxKS + ks) * 2 + part) * kFragBytes;
+__device__ __forceinline__ int frag_off(int rb, int ks, int nks, int part) {
+  return ((rb * nks + ks) * 2 + part) * kFragBytes;
 }
+
+constexpr int frag_capacity(int nrb) { return nrb * kAdjMaxKS < kAdjMaxFrags ? nrb * kAdjMaxKS : kAdjMaxFrags; }
 
 template <int PREC, int NRB>
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds_raw[NRB * kAdjMaxKS * 2 * kFragBytes];
+  // NRB * nks <= frag_capacity(NRB) (checked on the host)
+  __shared__ __attribute__((aligned(16))) uint8_t lds_raw[frag_capacity(NRB) * 2 * kFragBytes];
   __shared__ float s_red[kAdjThreads / 64];
   __shared__ double s_g[2][kAdjThreads / 64];
   lds_b* lds = (lds_b*)lds_raw;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb0 = blockIdx.y * a.rb_per_range;  // first row block of this range
+  const int nrb = min(NRB, (a.nl + 15) / 16 - rb0);
 
   // G's scale: a power of two with max |G| scale < 2^14 (FP16); 1 for BF16.
   float g_scale = 1.0f;
@@ -105,7 +116,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
   for (int it = threadIdx.x; it < n_items; it += kAdjThreads) {
     const int l = it & 63, f = it >> 6;
     const int rb = f / a.nks, ks = f - rb * a.nks;
-    const int i = 16 * rb + (l & 15), j0 = 32 * ks + 8 * (l >> 4);
+    const int i = 16 * (rb0 + rb) + (l & 15), j0 = 32 * ks + 8 * (l >> 4);
     float v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -120,17 +131,18 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
       hi[t] = h;
       lo[t] = w;
     }
-    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, 0) + l * 16) = hi;
-    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, 1) + l * 16) = lo;
+    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, a.nks, 0) + l * 16) = hi;
+    *reinterpret_cast<lds_v4u*>(lds + frag_off(rb, ks, a.nks, 1) + l * 16) = lo;
   }
   __syncthreads();
 
   const int n = lane & 15, jg = lane >> 4;
+  (void)nrb;
   const int64_t kb = static_cast<int64_t>(blockIdx.x) * a.slice;
   const int64_t ke = min(a.K, kb + a.slice);
   const float inv_y = static_cast<float>(1.0 / a.y_scale);
   const double y_lane = (a.m_first + (8 * jg) * a.dm) - a.m0;  // column 8 jg
-  const double x_lane = (a.l_first + (4 * jg) * a.dl) - a.l0;  // row 4 jg
+  const double x_lane = (a.l_first + (16 * rb0 + 4 * jg) * a.dl) - a.l0;  // row 16 rb0 + 4 jg
   const float ys0 = static_cast<float>(y_lane * a.y_scale), ystep = static_cast<float>(a.dm * a.y_scale);
   const float xs0 = static_cast<float>(x_lane), xstep = static_cast<float>(a.dl);
   double gl = 0.0, gm = 0.0;
@@ -173,8 +185,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
       zb = cmul(zb, s25);  // column 32 ks + 8 jg + 7 -> 32 (ks + 1) + 8 jg
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
-        const v4u gh = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, 0) + lane * 16);
-        const v4u gw = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, 1) + lane * 16);
+        const v4u gh = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, a.nks, 0) + lane * 16);
+        const v4u gw = *reinterpret_cast<const lds_v4u*>(lds + frag_off(rb, ks, a.nks, 1) + lane * 16);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           acc[rb][q] = mma<PREC>(gh, bh[q], acc[rb][q]);
@@ -241,8 +253,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
       sl += s_g[0][w];
       sm += s_g[1][w];
     }
-    a.partial[2 * blockIdx.x] = sl / g_scale;
-    a.partial[2 * blockIdx.x + 1] = sm / g_scale;
+    const int64_t slot = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;
+    a.partial[2 * slot] = sl / g_scale;
+    a.partial[2 * slot + 1] = sm / g_scale;
   }
 }
 
@@ -272,8 +285,8 @@ __global__ __launch_bounds__(256) void k_adjoint_sum(const double* __restrict__ 
 }
 
 template <int PREC>
-hipError_t launch_rb(int nrb, const AdjArgs& a, int n_wg, hipStream_t st) {
-  const dim3 g(n_wg), b(kAdjThreads);
+hipError_t launch_rb(int nrb, const AdjArgs& a, int n_wg, int n_ranges, hipStream_t st) {
+  const dim3 g(n_wg, n_ranges), b(kAdjThreads);
   switch (nrb) {
     case 1: hipLaunchKernelGGL((k_adjoint<PREC, 1>), g, b, 0, st, a); break;
     case 2: hipLaunchKernelGGL((k_adjoint<PREC, 2>), g, b, 0, st, a); break;
@@ -288,14 +301,31 @@ hipError_t launch_rb(int nrb, const AdjArgs& a, int n_wg, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Row ranges of a patch: each range's G fragments (its row blocks times the
+// k-steps) fit in LDS.
+struct RowRanges {
+  int nks, n_ranges, rb_per_range;
+};
+RowRanges row_ranges(const psf_src& s) {
+  RowRanges r;
+  r.nks = (s.nm + 31) / 32;
+  const int max_rb = std::min(kAdjMaxRB, kAdjMaxFrags / std::max(1, r.nks));
+  const int nb = (s.nl + 15) / 16;
+  r.n_ranges = (nb + max_rb - 1) / max_rb;
+  r.rb_per_range = (nb + r.n_ranges - 1) / r.n_ranges;
+  return r;
+}
+
 }  // namespace
 
 bool adjoint_reverse_ok(int prec, const psf_obs* o, const psf_src& s) {
-  return (prec == kSplitBF16 || prec == kSplitFP16) && o->K > 0 && s.nl <= 16 * kAdjMaxRB &&
-         s.nm <= 32 * kAdjMaxKS;
+  return (prec == kSplitBF16 || prec == kSplitFP16) && o->K > 0 && s.nm <= 32 * kAdjMaxKS &&
+         row_ranges(s).n_ranges <= kAdjMaxRanges;
 }
 
-size_t adjoint_reverse_partial_bytes() { return static_cast<size_t>(kAdjWG) * 2 * sizeof(double); }
+size_t adjoint_reverse_partial_bytes() {
+  return static_cast<size_t>(kAdjSlices) * kAdjMaxRanges * 2 * sizeof(double);
+}
 
 hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, const BinRec* rec,
                                   const float2* coef, const float* G, double* partial, double* grad,
@@ -306,9 +336,16 @@ hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, 
   a.G = G;
   a.partial = partial;
   a.K = o->K;
-  const int64_t per = (o->K + kAdjWG - 1) / kAdjWG;
+  // row ranges of equal size, each range's G fragments within LDS
+  const RowRanges rr = row_ranges(s);
+  a.nks = rr.nks;
+  a.rb_per_range = rr.rb_per_range;
+  const int n_ranges = rr.n_ranges;
+  // fewer k-slices when there are several ranges: about kAdjSlices workgroups
+  const int slices = std::max(1, kAdjSlices / n_ranges);
+  const int64_t per = (o->K + slices - 1) / slices;
   a.slice = std::max<int64_t>(64, (per + 63) / 64 * 64);
-  const int n_wg = static_cast<int>(std::min<int64_t>(kAdjWG, (o->K + a.slice - 1) / a.slice));
+  const int n_wg = static_cast<int>(std::min<int64_t>(slices, (o->K + a.slice - 1) / a.slice));
   a.l_first = s.l_first;
   a.m_first = s.m_first;
   a.dl = s.dl;
@@ -323,11 +360,11 @@ hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, 
   a.y_scale = std::ldexp(1.0, -e);
   a.nl = s.nl;
   a.nm = s.nm;
-  a.nks = (s.nm + 31) / 32;
-  const int nrb = (s.nl + 15) / 16;
-  hipError_t err = prec == kSplitFP16 ? launch_rb<kSplitFP16>(nrb, a, n_wg, st) : launch_rb<kSplitBF16>(nrb, a, n_wg, st);
+  const int nrb = a.rb_per_range;
+  hipError_t err = prec == kSplitFP16 ? launch_rb<kSplitFP16>(nrb, a, n_wg, n_ranges, st)
+                                      : launch_rb<kSplitBF16>(nrb, a, n_wg, n_ranges, st);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, st, partial, n_wg, grad);
+  hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, st, partial, n_wg * n_ranges, grad);
   return hipGetLastError();
 }
 

@@ -181,3 +181,35 @@ def test_backward_config3_sixteen_sources_match_single_calls(pk):
         one = pk.patch_backward(dobs, [srcs[s]], G[s * n:(s + 1) * n], "split_bf16", workspace=ws).cpu().numpy()
         assert np.array_equal(one[0], allg[s]), s
     assert np.all(np.isfinite(allg)) and np.all(np.abs(allg) > 0)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16", "fp32"])
+def test_backward_257_patches(pk, prec):
+    """257 x 257 patches: the reverse-mode kernel splits the rows into three
+    ranges (split forms), FP32 takes the five-patch form; both against the
+    FP64 analytic gradient."""
+    obs = ps.observation(1)
+    cell = 1.0 * ps.ARCSEC
+    srcs = [ps.Source.centred(0.6 * ps.DEG, -0.2 * ps.DEG, 257, cell),
+            ps.Source.centred(-0.3 * ps.DEG, 0.9 * ps.DEG, 257, cell)]
+    fluxes = [1.0, 0.4]
+    g = np.random.default_rng(13)
+    moved = [s.with_direction(s.l0 + g.normal(0, ps.ARCSEC), s.m0 + g.normal(0, ps.ARCSEC)) for s in srcs]
+    T = [(f * orc.patch_factored(obs, m)).astype(np.float32) for f, m in zip(fluxes, moved)]
+    T64 = [t.astype(np.float64) for t in T]
+    L_ref, g_ref, gf_ref = orc.loss_grad_analytic(obs, srcs, fluxes, T64)
+    P64 = [orc.patch_factored(obs, s) for s in srcs]
+    fscale = [2.0 * np.sum(np.abs((f * P - t) * P)) for f, P, t in zip(fluxes, P64, T64)]
+    L, g_lm, g_f = _gpu_loss_grad(pk, obs, srcs, fluxes, T, prec)
+    assert abs(L - L_ref) <= 1e-3 * L_ref
+    _check(g_lm, g_f, g_ref, gf_ref, f"257 {prec}", flux_scale=fscale)
+    dobs = pk.DeviceObservation(obs)
+    # a ragged 257 x 200 patch through the raw adjoint, cotangent from the oracle
+    rag = ps.Source.centred(0.2 * ps.DEG, 0.5 * ps.DEG, 257, cell, nm=200)
+    Tr = orc.patch_factored(obs, rag.with_direction(rag.l0 + ps.ARCSEC, rag.m0 - ps.ARCSEC))
+    _, g_rag, _ = orc.loss_grad_analytic(obs, [rag], [1.0], [Tr])
+    G = torch.as_tensor(2.0 * (orc.patch_factored(obs, rag) - Tr), dtype=torch.float32, device="cuda").reshape(-1)
+    got = pk.patch_backward(dobs, [rag], G, prec).cpu().numpy()
+    err = np.max(np.abs(got[0] - g_rag[0])) / np.max(np.abs(g_rag[0]))
+    print(f"257x200 {prec}: dir rel err {err:.2e}", flush=True)
+    assert err <= GRAD_TOL
