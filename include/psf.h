@@ -155,8 +155,7 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
  * definition [section 2.3, distorted-PSF equation] runs through D_k (its
  * derivative over the bin's samples [section 2.3 averaging]), the
  * linearised w-shift u'(l0, m0), v'(l0, m0) and the pixel offsets
- * x_i = l_i - l0, y_j = m_j - m0.  For split-BF16 and split-FP16 patches
- * of up to 288 columns (rows: up to 16 ranges of row blocks whose share of
+ * x_i = l_i - l0, y_j = m_j - m0.  For patches of up to 288 columns (rows: up to 16 ranges of row blocks whose share of
  * G fits in LDS, e.g. 2048 rows at 257 columns) it evaluates the sums per
  * visibility in reverse mode (G b and G (y b) on the matrix cores, G held
  * on chip); otherwise it

@@ -1,6 +1,6 @@
 // Reverse-mode adjoint of the patch for patches of up to 288 columns (and
-// rows within 16 ranges that fit in LDS) in the split-BF16 and split-FP16
-// forms.  The derivatives are those of the
+// rows within 16 ranges that fit in LDS) in the FP32, split-BF16 and
+// split-FP16 forms.  The derivatives are those of the
 // five-patch form in psf_backward.hip (derivation in k_decorr.hip),
 // regrouped per visibility:
 //   dL/dl0 = 2 Re sum_k [e0_k H_k + e2_k Hx_k + e3_k Hy_k]
@@ -111,8 +111,22 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
       g_scale = ldexpf(1.0f, 14 - e);
     }
   }
-  // G into LDS as split operand fragments; rows >= nl and columns >= nm are 0.
-  const int n_items = NRB * a.nks * 64;
+  // G into LDS as operand fragments; rows >= nl and columns >= nm are 0.
+  // FP32: per 32 columns eight 16x4 fragments of 64 floats (lane l: row
+  // l mod 16, column 4 k4 + l / 16), in the same 2 KiB as a split pair.
+  if constexpr (PREC == kFP32) {
+    const int n_f32 = NRB * a.nks * 8 * 64;
+    for (int it = threadIdx.x; it < n_f32; it += kAdjThreads) {
+      const int l = it & 63, f = it >> 6;
+      const int k4 = f & 7, f2 = f >> 3;
+      const int rb = f2 / a.nks, ks = f2 - rb * a.nks;
+      const int i = 16 * (rb0 + rb) + (l & 15), j = 32 * ks + 4 * k4 + (l >> 4);
+      const float v = (i < a.nl && j < a.nm) ? a.G[static_cast<int64_t>(i) * a.nm + j] : 0.0f;
+      *reinterpret_cast<__attribute__((address_space(3))) float*>(lds + frag_off(rb, ks, a.nks, 0) + k4 * 256 +
+                                                                    l * 4) = v;
+    }
+  }
+  const int n_items = PREC == kFP32 ? 0 : NRB * a.nks * 64;
   for (int it = threadIdx.x; it < n_items; it += kAdjThreads) {
     const int l = it & 63, f = it >> 6;
     const int rb = f / a.nks, ks = f - rb * a.nks;
@@ -141,7 +155,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
   const int64_t kb = static_cast<int64_t>(blockIdx.x) * a.slice;
   const int64_t ke = min(a.K, kb + a.slice);
   const float inv_y = static_cast<float>(1.0 / a.y_scale);
-  const double y_lane = (a.m_first + (8 * jg) * a.dm) - a.m0;  // column 8 jg
+  // first column of the lane: 8 jg (16-bit operands), jg (FP32 operands)
+  const double y_lane = (a.m_first + (PREC == kFP32 ? jg : 8 * jg) * a.dm) - a.m0;
   const double x_lane = (a.l_first + (16 * rb0 + 4 * jg) * a.dl) - a.l0;  // row 16 rb0 + 4 jg
   const float ys0 = static_cast<float>(y_lane * a.y_scale), ystep = static_cast<float>(a.dm * a.y_scale);
   const float xs0 = static_cast<float>(x_lane), xstep = static_cast<float>(a.dl);
@@ -152,13 +167,35 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
     const BinRec* r = a.rec + (ok ? kk : ke - 1);
     const double up = r->up, vp = r->vp;
     cf32 zb = expi_turns(vp * y_lane);
-    const cf32 s1 = expi_turns(vp * a.dm), s25 = expi_turns(vp * (25.0 * a.dm));
     v4f acc[NRB][4];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[rb][q] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < a.nks; ++ks) {
+    if constexpr (PREC == kFP32) {
+      // one column per lane and 16x16x4 step: columns jg, jg + 4, ...
+      const cf32 s4 = expi_turns(vp * (4.0 * a.dm));
+      for (int ks = 0; ks < a.nks; ++ks) {
+#pragma unroll
+        for (int k4 = 0; k4 < 8; ++k4) {
+          const float y = ys0 + static_cast<float>(32 * ks + 4 * k4) * ystep;
+          const cf32 b = zb;
+          zb = cmul(zb, s4);
+          const float yr = y * b.re, yi = y * b.im;
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) {
+            const float g = *reinterpret_cast<const __attribute__((address_space(3))) float*>(
+                lds + frag_off(rb, ks, a.nks, 0) + k4 * 256 + lane * 4);
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, b.re, acc[rb][0], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, b.im, acc[rb][1], 0, 0, 0);
+            acc[rb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yr, acc[rb][2], 0, 0, 0);
+            acc[rb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yi, acc[rb][3], 0, 0, 0);
+          }
+        }
+      }
+    }
+    const cf32 s1 = expi_turns(vp * a.dm), s25 = expi_turns(vp * (25.0 * a.dm));
+    for (int ks = 0; ks < (PREC == kFP32 ? 0 : a.nks); ++ks) {
       // b and y b at columns 32 ks + 8 jg + t, t = 0..7: re, im, y re, y im
       v4u bh[4], bl[4];
 #pragma unroll
@@ -319,7 +356,7 @@ RowRanges row_ranges(const psf_src& s) {
 }  // namespace
 
 bool adjoint_reverse_ok(int prec, const psf_obs* o, const psf_src& s) {
-  return (prec == kSplitBF16 || prec == kSplitFP16) && o->K > 0 && s.nm <= 32 * kAdjMaxKS &&
+  return (prec == kSplitBF16 || prec == kSplitFP16 || prec == kFP32) && o->K > 0 && s.nm <= 32 * kAdjMaxKS &&
          row_ranges(s).n_ranges <= kAdjMaxRanges;
 }
 
@@ -362,6 +399,7 @@ hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, 
   a.nm = s.nm;
   const int nrb = a.rb_per_range;
   hipError_t err = prec == kSplitFP16 ? launch_rb<kSplitFP16>(nrb, a, n_wg, n_ranges, st)
+                   : prec == kFP32    ? launch_rb<kFP32>(nrb, a, n_wg, n_ranges, st)
                                       : launch_rb<kSplitBF16>(nrb, a, n_wg, n_ranges, st);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_adjoint_sum, dim3(1), dim3(256), 0, st, partial, n_wg * n_ranges, grad);

@@ -213,3 +213,18 @@ def test_backward_257_patches(pk, prec):
     err = np.max(np.abs(got[0] - g_rag[0])) / np.max(np.abs(g_rag[0]))
     print(f"257x200 {prec}: dir rel err {err:.2e}", flush=True)
     assert err <= GRAD_TOL
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
+def test_backward_wide_patch_five_patch_form(pk, prec):
+    """A patch wider than the reverse-mode kernel takes (300 columns) goes
+    through the five derivative patches; against the FP64 gradient."""
+    obs = ps.observation(1)
+    src = ps.Source.centred(0.4 * ps.DEG, 0.1 * ps.DEG, 64, 1.5 * ps.ARCSEC, nm=300)
+    T = orc.patch_factored(obs, src.with_direction(src.l0 - ps.ARCSEC, src.m0 + 0.5 * ps.ARCSEC))
+    _, g_ref, _ = orc.loss_grad_analytic(obs, [src], [1.0], [T])
+    G = torch.as_tensor(2.0 * (orc.patch_factored(obs, src) - T), dtype=torch.float32, device="cuda").reshape(-1)
+    got = pk.patch_backward(pk.DeviceObservation(obs), [src], G, prec).cpu().numpy()
+    err = np.max(np.abs(got[0] - g_ref[0])) / np.max(np.abs(g_ref[0]))
+    print(f"64x300 {prec}: dir rel err {err:.2e}", flush=True)
+    assert err <= GRAD_TOL
