@@ -718,3 +718,49 @@ def test_method2_on_grid_visibilities_equals_direct_sum():
         ref += 2.0 * float(np.float32(w)) * d * np.cos(2 * math.pi * (a * du * X + b * du * Y))
     assert np.max(np.abs(Q - ref)) < 1e-11 * np.max(np.abs(ref))
     assert np.max(np.abs(Q - orc.method2_effective_psf(obs, N, cell))) > 0.1 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- CLEAN with Method-2 PSFs
+def _placed(Q, i, j, nl, nm):
+    """Q (centred N x N) with its centre on image pixel (i, j); outside 0."""
+    N = Q.shape[0]
+    out = np.zeros((nl, nm))
+    for a in range(nl):
+        for b in range(nm):
+            u, v = a - i + N // 2, b - j + N // 2
+            if 0 <= u < N and 0 <= v < N:
+                out[a, b] = Q[u, v]
+    return out
+
+
+@pytest.mark.parametrize("pix", [(20, 11), (2, 30)])
+def test_method2_clean_single_source_residual_is_geometric(cfg1, pix):
+    """A dirty image that is one Method-2 PSF laid on a pixel (near the edge
+    too, where the PSF is cut): every cycle finds that pixel and removes the
+    fraction gain of what is left."""
+    obs, _ = cfg1
+    grid = _image_grid()
+    N, cell = 32, grid.dl
+    Peff = orc.method2_effective_psf(obs, N, cell)
+    i0, j0 = pix
+    l0, m0 = grid.l_first + i0 * grid.dl, grid.m_first + j0 * grid.dm
+    Q = orc.method2_patch(Peff, cell, l0, m0, 30.0, 1e6, 1.4e9)
+    dirty = 0.7 * _placed(Q, i0, j0, grid.nl, grid.nm)
+    gain, n = 0.3, 6
+    res, comps = orc.hogbom_clean_method2(Peff, grid, dirty, gain, n, 30.0, 1e6, 1.4e9)
+    assert [(i, j) for i, j, _ in comps] == [(i0, j0)] * n
+    assert np.max(np.abs(res - (1 - gain) ** n * dirty)) < 1e-12 * np.max(np.abs(dirty))
+    assert abs(sum(a for _, _, a in comps) - (1 - (1 - gain) ** n) * dirty[i0, j0]) < 1e-12 * abs(dirty[i0, j0])
+
+
+def test_method2_clean_at_the_phase_centre_uses_the_effective_psf(cfg1):
+    """At the pixel of the phase centre D^ = 1, so the subtracted PSF is the
+    effective PSF itself."""
+    obs, _ = cfg1
+    grid = ps.Source.centred(0.0, 0.0, 33, 4.0 * ps.ARCSEC)
+    N = 64
+    Peff = orc.method2_effective_psf(obs, N, grid.dl)
+    dirty = _placed(Peff, 16, 16, 33, 33)
+    res, comps = orc.hogbom_clean_method2(Peff, grid, dirty, 1.0, 1, 30.0, 1e6, 1.4e9)
+    assert comps[0][:2] == (16, 16)
+    assert np.max(np.abs(res)) < 1e-12 * np.max(np.abs(dirty))
