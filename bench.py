@@ -207,7 +207,17 @@ def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     _, comps = pk.clean_hogbom(dobs, grid, dirty, cycles, 0.1, 0.0, prec=prec, workspace=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"image": [grid.nl, grid.nm], "cycles": len(comps), "ms_per_cycle": dt / max(1, len(comps)) * 1e3}
+    # the same image with Method-2 PSFs (512 x 512 spectrum: covers the image from any peak)
+    S = pk.method2_spectrum(dobs, 512, grid.dl, prec=prec, workspace=ws)
+    pk.clean_hogbom_method2(S, grid, dirty, 2, 20.0, 2.5e7, 1.4e9, 0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, comps2 = pk.clean_hogbom_method2(S, grid, dirty, 10 * cycles, 20.0, 2.5e7, 1.4e9, 0.1)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t0
+    return {"image": [grid.nl, grid.nm], "cycles": len(comps), "ms_per_cycle": dt / max(1, len(comps)) * 1e3,
+            "method2_psf_grid": [512, 512], "method2_cycles": len(comps2),
+            "method2_ms_per_cycle": dt2 / max(1, len(comps2)) * 1e3}
 
 
 def cpu_baseline(obs, src, n_bl_sub):

@@ -234,6 +234,20 @@ int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual,
                      double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
                      int32_t* n_comp, void* ws, size_t ws_bytes, void* stream);
 
+/* Hogbom CLEAN with Method-2 PSFs [Algorithm 2 with the section 3.2
+ * approximation]: as psf_clean_hogbom, but the PSF of each peak's direction
+ * is the Method-2 patch (psf_method2_patch from the spectrum S of
+ * psf_method2_spectrum, N x N at the image's cell, which must be square),
+ * laid with its centre (offset 0, index N/2) on the peak pixel; image
+ * pixels beyond its extent are not changed.  dt_bin, dnu_bin, nu as for
+ * psf_method2_patch.  Synchronises the stream once per cycle: not
+ * capturable.  ws sized with psf_clean_method2_workspace_bytes. */
+int psf_clean_method2_workspace_bytes(int32_t N, const psf_src* h_grid, size_t* out);
+int psf_clean_hogbom_method2(int32_t N, const float* S, const psf_src* h_grid, float* residual, int32_t max_iter,
+                             double gain, double threshold, double dt_bin, double dnu_bin, double nu,
+                             int32_t* comp_i, int32_t* comp_j, float* comp_amp, int32_t* n_comp, void* ws,
+                             size_t ws_bytes, void* stream);
+
 /* Times candidate launch shapes for these sources with HIP events and
  * writes a JSON tuning table (host buffer json_out, capacity json_cap).
  * Synchronises the stream: not capturable. */

@@ -74,6 +74,12 @@ _SIGNATURES = {
     "psf_clean_hogbom": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
+    "psf_clean_method2_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(PsfSrc),
+                                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "psf_clean_hogbom_method2": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, _P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P,
+                                                ctypes.c_size_t, _P]),
     "psf_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "psf_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "psf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -485,4 +491,28 @@ def clean_hogbom(dobs: DeviceObservation, grid, dirty, max_iter: int, gain: floa
     _check(lib().psf_clean_hogbom(ctypes.byref(dobs.struct), ctypes.byref(h), res.data_ptr(), int(max_iter),
                                   float(gain), float(threshold), _prec(prec), ci, cj, ca, ctypes.byref(n),
                                   ws.data_ptr(), ws.numel(), _stream_handle()))
+    return res, [(ci[k], cj[k], ca[k]) for k in range(n.value)]
+
+
+def clean_hogbom_method2(S, grid, dirty, max_iter: int, dt_bin: float, dnu_bin: float, nu: float,
+                         gain: float = 0.1, threshold: float = 0.0, workspace: Optional[Workspace] = None):
+    """Hogbom CLEAN with the Method-2 PSF at every peak
+    (``psf_clean_hogbom_method2``); ``S`` from ``method2_spectrum`` at the
+    image's cell.  Returns (residual tensor, list of (i, j, amplitude))."""
+    torch = _torch()
+    N = int(S.shape[0])
+    h = make_src(grid)
+    need = ctypes.c_size_t(0)
+    _check(lib().psf_clean_method2_workspace_bytes(N, ctypes.byref(h), ctypes.byref(need)))
+    ws = (workspace or Workspace(S.device)).get(need.value)
+    res = dirty.to(device=S.device, dtype=torch.float32).contiguous().clone()
+    Sr = torch.view_as_real(S) if S.is_complex() else S
+    ci = (ctypes.c_int32 * max(1, max_iter))()
+    cj = (ctypes.c_int32 * max(1, max_iter))()
+    ca = (ctypes.c_float * max(1, max_iter))()
+    n = ctypes.c_int32(0)
+    _check(lib().psf_clean_hogbom_method2(N, Sr.data_ptr(), ctypes.byref(h), res.data_ptr(), int(max_iter),
+                                          float(gain), float(threshold), float(dt_bin), float(dnu_bin), float(nu),
+                                          ci, cj, ca, ctypes.byref(n), ws.data_ptr(), ws.numel(),
+                                          _stream_handle()))
     return res, [(ci[k], cj[k], ca[k]) for k in range(n.value)]

@@ -6,6 +6,7 @@
 // kernels; the host reads back the peak (one synchronisation per cycle) to
 // place the next PSF.
 #include <algorithm>
+#include <cmath>
 
 #include "psf_host.hpp"
 
@@ -78,6 +79,44 @@ __global__ __launch_bounds__(kMaxThreads) void k_clean_subtract(float* __restric
   if (i >= n) return;
   const float scale = gain * pk->val / P[pk->idx];
   res[i] -= scale * P[i];
+}
+
+// residual -= gain * peak * P / P(centre), P a centred N x N PSF laid with
+// its centre on pixel (pi, pj); pixels beyond its extent are not changed.
+__global__ __launch_bounds__(kMaxThreads) void k_clean_subtract_laid(float* __restrict__ res, int nl, int nm,
+                                                                      const float* __restrict__ P, int N, int pi,
+                                                                      int pj, const Peak* __restrict__ pk,
+                                                                      float gain) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nl) * nm) return;
+  const int a = static_cast<int>(idx / nm), b = static_cast<int>(idx - static_cast<int64_t>(a) * nm);
+  const int u = a - pi + N / 2, v = b - pj + N / 2;
+  if (u < 0 || u >= N || v < 0 || v >= N) return;
+  const float scale = gain * pk->val / P[static_cast<int64_t>(N / 2) * N + N / 2];
+  res[idx] -= scale * P[static_cast<int64_t>(u) * N + v];
+}
+
+struct M2CleanLayout {
+  size_t part, peak, P, work, total;
+};
+
+M2CleanLayout m2_clean_layout(int32_t N) {
+  M2CleanLayout L;
+  L.part = 0;
+  L.peak = align_up(kMaxBlocks * sizeof(Peak), 256);
+  L.P = L.peak + align_up(sizeof(Peak), 256);
+  L.work = L.P + align_up(static_cast<size_t>(N) * N * sizeof(float), 256);
+  L.total = L.work + align_up(static_cast<size_t>(N) * N * sizeof(float2), 256);
+  return L;
+}
+
+int validate_m2_clean(int32_t N, const psf_src* grid) {
+  int st;
+  if ((st = validate_src(grid, 0)) != PSF_OK) return st;
+  if (N < 16 || N > 4096 || (N & (N - 1)) != 0) return fail(PSF_EINVAL, "N=%d must be a power of two in 16..4096", N);
+  if (!(std::fabs(grid->dl - grid->dm) <= 1e-12 * std::fabs(grid->dl)))
+    return fail(PSF_EINVAL, "Method-2 CLEAN needs square cells (dl = dm)");
+  return PSF_OK;
 }
 
 struct CleanLayout {
@@ -172,6 +211,70 @@ int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual,
     hipLaunchKernelGGL(k_clean_subtract, dim3(static_cast<unsigned>((n + kMaxThreads - 1) / kMaxThreads)),
                        dim3(kMaxThreads), 0, s, residual, P, n, peak, static_cast<float>(gain));
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_clean_subtract launch");
+    comp_i[it] = i;
+    comp_j[it] = j;
+    comp_amp[it] = static_cast<float>(gain * hp.val);
+    *n_comp = it + 1;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+int psf_clean_method2_workspace_bytes(int32_t N, const psf_src* h_grid, size_t* out) {
+  clear_error();
+  int st;
+  if ((st = validate_m2_clean(N, h_grid)) != PSF_OK) return st;
+  if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
+  *out = m2_clean_layout(N).total;
+  return PSF_OK;
+}
+
+int psf_clean_hogbom_method2(int32_t N, const float* S, const psf_src* h_grid, float* residual, int32_t max_iter,
+                             double gain, double threshold, double dt_bin, double dnu_bin, double nu,
+                             int32_t* comp_i, int32_t* comp_j, float* comp_amp, int32_t* n_comp, void* ws,
+                             size_t ws_bytes, void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_m2_clean(N, h_grid)) != PSF_OK) return st;
+  if (S == nullptr || residual == nullptr || n_comp == nullptr) return fail(PSF_EINVAL, "S, residual or n_comp is NULL");
+  if (max_iter < 0) return fail(PSF_EINVAL, "max_iter < 0");
+  if (max_iter > 0 && (comp_i == nullptr || comp_j == nullptr || comp_amp == nullptr))
+    return fail(PSF_EINVAL, "component arrays are NULL");
+  if (!(gain > 0.0 && gain <= 1.0)) return fail(PSF_EINVAL, "gain %g outside (0, 1]", gain);
+  if (!(threshold >= 0.0)) return fail(PSF_EINVAL, "threshold must be >= 0");
+  const M2CleanLayout L = m2_clean_layout(N);
+  if (ws == nullptr || ws_bytes < L.total)
+    return fail(PSF_EWORKSPACE, "psf_clean_hogbom_method2 needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  Peak* part = reinterpret_cast<Peak*>(w + L.part);
+  Peak* peak = reinterpret_cast<Peak*>(w + L.peak);
+  float* P = reinterpret_cast<float*>(w + L.P);
+  void* work = w + L.work;
+  const size_t work_bytes = L.total - L.work;
+  const int64_t n = static_cast<int64_t>(h_grid->nl) * h_grid->nm;
+  const int nb = static_cast<int>(std::min<int64_t>(kMaxBlocks, (n + kMaxThreads - 1) / kMaxThreads));
+  *n_comp = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(kMaxThreads), 0, s, residual, n, part);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kMaxThreads), 0, s, part, nb, peak);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "peak search launch");
+    Peak hp;
+    if ((e = hipMemcpyAsync(&hp, peak, sizeof(Peak), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "peak read-back");
+    if (hp.idx < 0 || hp.idx >= n || !(hp.absval >= threshold) || hp.absval == 0.0f) break;
+    const int i = static_cast<int>(hp.idx / h_grid->nm), j = static_cast<int>(hp.idx % h_grid->nm);
+    const double dir[2] = {h_grid->l_first + i * h_grid->dl, h_grid->m_first + j * h_grid->dm};
+    if ((st = psf_method2_patch(N, h_grid->dl, S, 1, dir, dt_bin, dnu_bin, nu, P, work, work_bytes, stream)) !=
+        PSF_OK)
+      return st;
+    hipLaunchKernelGGL(k_clean_subtract_laid, dim3(static_cast<unsigned>((n + kMaxThreads - 1) / kMaxThreads)),
+                       dim3(kMaxThreads), 0, s, residual, h_grid->nl, h_grid->nm, P, N, i, j, peak,
+                       static_cast<float>(gain));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_clean_subtract_laid launch");
     comp_i[it] = i;
     comp_j[it] = j;
     comp_amp[it] = static_cast<float>(gain * hp.val);

@@ -223,3 +223,20 @@ def test_successful_call_clears_last_error(L):
     assert L.psf_last_error()
     assert L.psf_method2_workspace_bytes(ctypes.byref(o), 128, 1, 1, ctypes.byref(out)) == pk.PSF_OK
     assert L.psf_last_error() == b""
+
+
+def test_method2_clean_host_side_errors(L):
+    out = ctypes.c_size_t(0)
+    sq = fake_src(dl=1e-5, dm=1e-5)
+    assert L.psf_clean_method2_workspace_bytes(128, ctypes.byref(sq), ctypes.byref(out)) == pk.PSF_OK
+    assert out.value >= 128 * 128 * 12
+    rect = fake_src(dl=1e-5, dm=2e-5)
+    assert L.psf_clean_method2_workspace_bytes(128, ctypes.byref(rect), ctypes.byref(out)) == pk.PSF_EINVAL
+    assert L.psf_clean_method2_workspace_bytes(100, ctypes.byref(sq), ctypes.byref(out)) == pk.PSF_EINVAL
+    n = ctypes.c_int32(0)
+    st, _ = status_of(L.psf_clean_hogbom_method2, 128, FAKE, ctypes.byref(sq), FAKE, 5, 1.5, 0.0, 20.0, 1e6, 1.4e9,
+                      FAKE, FAKE, FAKE, ctypes.byref(n), FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL
+    st, _ = status_of(L.psf_clean_hogbom_method2, 128, FAKE, ctypes.byref(sq), FAKE, 5, 0.5, 0.0, 20.0, 1e6, 1.4e9,
+                      FAKE, FAKE, FAKE, ctypes.byref(n), FAKE, 64, None)
+    assert st == pk.PSF_EWORKSPACE

@@ -64,3 +64,23 @@ def test_clean_threshold_stops_before_any_cycle(pk):
     d = torch.as_tensor(dirty, dtype=torch.float32)
     res, comps = pk.clean_hogbom(dobs, grid, d, 5, 0.2, float(np.max(np.abs(dirty))) * 1.01)
     assert comps == [] and torch.equal(res.cpu(), d)
+
+
+@pytest.mark.parametrize("N", [128, 32])
+def test_clean_with_method2_psfs_matches_oracle(pk, N):
+    """CLEAN with the Method-2 PSF at every peak (N = 128 covers the 65-pixel
+    image from any peak; N = 32 is cut, so pixels beyond its extent stay)."""
+    obs, grid, dirty = _setup([(10, 12, 1.0), (50, 44, 0.45), (33, 52, 0.2)])
+    dt, dnu, nu = 30.0, 1e6, 1.4e9
+    Peff = orc.method2_effective_psf(obs, N, grid.dl)
+    ref_res, ref_comps = orc.hogbom_clean_method2(Peff, grid, dirty, 0.5, 10, dt, dnu, nu)
+    S = pk.method2_spectrum(pk.DeviceObservation(obs), N, grid.dl)
+    res, comps = pk.clean_hogbom_method2(S, grid, torch.as_tensor(dirty, dtype=torch.float32), 10, dt, dnu, nu,
+                                         gain=0.5)
+    scale = np.max(np.abs(dirty))
+    assert [c[:2] for c in comps] == [c[:2] for c in ref_comps]
+    amp_err = max(abs(a - b[2]) for (_, _, a), b in zip(comps, ref_comps)) / scale
+    res_err = np.max(np.abs(res.double().cpu().numpy() - ref_res)) / scale
+    print(f"method-2 CLEAN N={N}: {len(comps)} components, amplitude err {amp_err:.2e}, residual err {res_err:.2e}",
+          flush=True)
+    assert amp_err <= TOL and res_err <= TOL
