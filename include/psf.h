@@ -226,7 +226,8 @@ int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, con
  * decorrelation factors computed), subtracts gain * peak * PSF / PSF(peak)
  * and records the component (pixel comp_i, comp_j, amplitude gain * peak;
  * host arrays of max_iter entries; *n_comp receives the count).  Stops
- * early when |peak| < threshold.  gain in (0, 1].  Synchronises the stream
+ * early when |peak| < threshold; an observation without visibilities
+ * (K = 0, a zero PSF) runs no cycle.  gain in (0, 1].  Synchronises the stream
  * once per cycle to read the peak: not capturable.  ws sized with
  * psf_clean_workspace_bytes. */
 int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int prec, size_t* out);

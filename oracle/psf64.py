@@ -86,7 +86,7 @@ def bin_table(obs) -> BinTable:
         c0_l.append(F * nc)
         c1_l.append(np.minimum(n_ch, (F + 1) * nc))
         tb_l.append(int(obs.bl_tboff[b]) + T)
-    cat = lambda xs: np.concatenate(xs).astype(np.int64)
+    cat = lambda xs: np.concatenate(xs).astype(np.int64) if xs else np.zeros(0, np.int64)
     tab = BinTable(cat(b_l), cat(t0_l), cat(t1_l), cat(c0_l), cat(c1_l), cat(tb_l))
     assert len(tab.b) == int(obs.bl_koff[-1]), "bin count disagrees with bl_koff"
     return tab

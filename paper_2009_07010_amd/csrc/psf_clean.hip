@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_clean_subtract(float* __restric
                                                                  int64_t n, const Peak* __restrict__ pk, float gain) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x;
   if (i >= n) return;
-  const float scale = gain * pk->val / P[pk->idx];
+  const float p0 = P[pk->idx];
+  const float scale = p0 != 0.0f ? gain * pk->val / p0 : 0.0f;  // a zero PSF subtracts nothing
   res[i] -= scale * P[i];
 }
 
@@ -188,6 +189,7 @@ int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual,
   const int64_t n = static_cast<int64_t>(h_grid->nl) * h_grid->nm;
   const int nb = static_cast<int>(std::min<int64_t>(kMaxBlocks, (n + kMaxThreads - 1) / kMaxThreads));
   *n_comp = 0;
+  if (obs->K == 0) return PSF_OK;  // no visibilities: the PSF is zero, nothing to subtract
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(kMaxThreads), 0, s, residual, n, part);
     hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kMaxThreads), 0, s, part, nb, peak);

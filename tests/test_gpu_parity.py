@@ -224,3 +224,38 @@ def test_single_source_patch_graph_capture_and_replay(cfg1):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), rep
     assert orc.peak_normalised_error(out.double().cpu().numpy(), P)[0] < TOL
+
+
+def _empty_observation():
+    """No baselines: K = 0 (every sum over visibilities is empty)."""
+    return ps.Observation(ant_enu=np.zeros((2, 3)), bl_ant=np.zeros((0, 2), np.int32), times_s=np.zeros(4),
+                          uvw_m=np.zeros((0, 4, 3)), freq_hz=np.array([1.4e9]), bl_bin=np.zeros((0, 2), np.int32),
+                          bl_koff=np.zeros(1, np.int64), bl_tboff=np.zeros(1, np.int64), uvw_c_m=np.zeros((0, 3)),
+                          W=np.zeros(0, np.float32))
+
+
+def test_empty_observation_through_every_entry_point():
+    """K = 0: the patch, the batched patches, the exact-w patch, the Method-2
+    spectrum and patches and the adjoint are all zero, and CLEAN runs no
+    cycle; the FP64 oracle's patch is zero too."""
+    obs = _empty_observation()
+    assert obs.K == 0
+    src = ps.Source.centred(0.01, -0.02, 33, 2.0 * ps.ARCSEC)
+    assert np.all(orc.patch_factored(obs, src) == 0.0)
+    dobs = pk.DeviceObservation(obs)
+    assert pk.decorr(dobs, src.l0, src.m0).numel() == 0
+    for prec in ACCURATE:
+        assert torch.count_nonzero(pk.patch(dobs, src, prec=prec)).item() == 0
+    srcs = [src, ps.Source.centred(0.02, 0.0, 65, 2.0 * ps.ARCSEC)]
+    assert torch.count_nonzero(pk.patch_batched(dobs, srcs)).item() == 0
+    P, n = pk.patch_fullw(dobs, src)
+    assert n == 1 and torch.count_nonzero(P).item() == 0
+    S = pk.method2_spectrum(dobs, 64, src.dl)
+    assert torch.count_nonzero(pk.method2_patches(S, src.dl, [(0.01, 0.0)], 20.0, 1e6, 1.4e9)).item() == 0
+    G = torch.ones(sum(s.nl * s.nm for s in srcs), device="cuda")
+    for prec in ("split_bf16", "fp32"):
+        assert torch.count_nonzero(pk.patch_backward(dobs, srcs, G, prec)).item() == 0
+    dirty = torch.ones((33, 33))
+    res, comps = pk.clean_hogbom(dobs, src, dirty, 5)
+    torch.cuda.synchronize()
+    assert comps == [] and torch.equal(res.cpu(), dirty)

@@ -764,3 +764,15 @@ def test_method2_clean_at_the_phase_centre_uses_the_effective_psf(cfg1):
     res, comps = orc.hogbom_clean_method2(Peff, grid, dirty, 1.0, 1, 30.0, 1e6, 1.4e9)
     assert comps[0][:2] == (16, 16)
     assert np.max(np.abs(res)) < 1e-12 * np.max(np.abs(dirty))
+
+
+def test_empty_observation_gives_empty_sums():
+    """No baselines: no bins, no factors, a zero patch (empty sums)."""
+    obs = ps.Observation(ant_enu=np.zeros((2, 3)), bl_ant=np.zeros((0, 2), np.int32), times_s=np.zeros(4),
+                         uvw_m=np.zeros((0, 4, 3)), freq_hz=np.array([1.4e9]), bl_bin=np.zeros((0, 2), np.int32),
+                         bl_koff=np.zeros(1, np.int64), bl_tboff=np.zeros(1, np.int64), uvw_c_m=np.zeros((0, 3)),
+                         W=np.zeros(0, np.float32))
+    src = ps.Source.centred(0.01, -0.02, 9, 2.0 * ps.ARCSEC)
+    assert orc.decorr(obs, 0.01, -0.02).shape == (0,)
+    assert np.all(orc.patch_factored(obs, src) == 0.0)
+    assert np.all(orc.patch_fullw(obs, src) == 0.0)
