@@ -217,6 +217,17 @@ int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, con
                       double dt_bin, double dnu_bin, double nu, float* P, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* The flux of the patch-fitting model flux_s P_s and its adjoint, for
+ * n_src sources whose patches (npix pixels each) are concatenated (device,
+ * float).  psf_flux_scale: out[s][p] = flux[s] P[s][p].  psf_flux_backward:
+ * given dL/dout, writes G[s][p] = flux[s] dL/dout[s][p] (float, the
+ * cotangent psf_patch_backward takes) and grad_flux[s] = sum_p dL/dout[s][p]
+ * P[s][p] (device double, FP64 products and sums in a fixed order).  flux is
+ * a device float array [n_src].  n_src in 1..65535, npix in 1..2^31. */
+int psf_flux_scale(int32_t n_src, int64_t npix, const float* flux, const float* P, float* out, void* stream);
+int psf_flux_backward(int32_t n_src, int64_t npix, const float* flux, const float* P, const float* grad_out,
+                      float* G, double* grad_flux, void* stream);
+
 /* Hogbom CLEAN with position-dependent PSFs [Algorithm 2]: up to max_iter
  * minor cycles on the image `residual` (device, float [nl][nm] on the grid
  * of h_grid, whose l0, m0 are ignored; in: the dirty image, out: the

@@ -80,6 +80,8 @@ _SIGNATURES = {
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_double, _P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P,
                                                 ctypes.c_size_t, _P]),
+    "psf_flux_scale": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
+    "psf_flux_backward": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, _P, _P]),
     "psf_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "psf_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "psf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -371,7 +373,7 @@ def _psf_patch_fn():
         [n_src]; ``grids`` gives each source's fixed pixel grid (l_first,
         m_first, dl, dm, nl, nm, all patches the same size).  The backward
         returns dLoss/d(lm0) from the library's adjoint (``psf_patch_backward``)
-        and dLoss/d(flux) = sum(grad_out * P_s).
+        and dLoss/d(flux) = sum(grad_out * P_s) (``psf_flux_backward``).
         """
 
         @staticmethod
@@ -386,18 +388,25 @@ def _psf_patch_fn():
             P = torch.empty((len(srcs), nl, nm), dtype=torch.float32, device=dobs.device)
             for s, src in enumerate(srcs):
                 patch(dobs, src, prec=prec, out=P[s], workspace=ws)
-            f = flux.detach().to(device=dobs.device, dtype=torch.float32)
+            f = flux.detach().to(device=dobs.device, dtype=torch.float32).contiguous()
+            out = torch.empty_like(P)
+            _check(lib().psf_flux_scale(len(srcs), nl * nm, f.data_ptr(), P.data_ptr(), out.data_ptr(),
+                                        _stream_handle()))
             ctx.save_for_backward(P, f)
             ctx.srcs, ctx.dobs, ctx.prec, ctx.ws = srcs, dobs, prec, ws
             ctx.lm_device, ctx.flux_device, ctx.flux_dtype = lm0.device, flux.device, flux.dtype
-            return f[:, None, None] * P
+            return out
 
         @staticmethod
         def backward(ctx, grad_out):
             P, f = ctx.saved_tensors
-            grad_flux = (grad_out.double() * P.double()).sum(dim=(1, 2))
-            grad_flux = grad_flux.to(device=ctx.flux_device, dtype=ctx.flux_dtype)
-            G = (grad_out.double() * f.double()[:, None, None]).to(torch.float32).reshape(-1)
+            n, nl, nm = P.shape
+            go = grad_out.to(device=P.device, dtype=torch.float32).contiguous()
+            G = torch.empty(n * nl * nm, dtype=torch.float32, device=P.device)
+            gflux = torch.empty(n, dtype=torch.float64, device=P.device)
+            _check(lib().psf_flux_backward(n, nl * nm, f.data_ptr(), P.data_ptr(), go.data_ptr(), G.data_ptr(),
+                                           gflux.data_ptr(), _stream_handle()))
+            grad_flux = gflux.to(device=ctx.flux_device, dtype=ctx.flux_dtype)
             grad_lm = patch_backward(ctx.dobs, ctx.srcs, G, ctx.prec, ctx.ws).to(ctx.lm_device)
             return grad_lm, grad_flux, None, None, None, None
 

@@ -94,7 +94,75 @@ size_t backward_workspace(const psf_obs* o, int n_src, const psf_src* h_srcs, in
 
 }  // namespace psf
 
+namespace psf {
+namespace {
+
+// out[s][p] = flux[s] P[s][p]
+__global__ __launch_bounds__(256) void k_flux_scale(const float* __restrict__ flux, const float* __restrict__ P,
+                                                    int64_t npix, float* __restrict__ out) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int64_t e = static_cast<int64_t>(blockIdx.y) * npix + p;
+  out[e] = flux[blockIdx.y] * P[e];
+}
+
+// One block per source: G = flux dL/dout (rounded from FP64) and
+// dL/dflux = sum_p dL/dout P in FP64, reduced in a fixed order.
+__global__ __launch_bounds__(256) void k_flux_backward(const float* __restrict__ flux, const float* __restrict__ P,
+                                                       const float* __restrict__ gout, int64_t npix,
+                                                       float* __restrict__ G, double* __restrict__ grad_flux) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * npix;
+  const double f = flux[blockIdx.x];
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < npix; p += 256) {
+    const double g = gout[base + p];
+    G[base + p] = static_cast<float>(g * f);
+    acc += g * static_cast<double>(P[base + p]);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) grad_flux[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+int validate_flux(int32_t n_src, int64_t npix) {
+  if (n_src < 1 || n_src > 65535) return fail(PSF_EINVAL, "n_src=%d outside 1..65535", n_src);
+  if (npix < 1 || npix > (int64_t(1) << 31)) return fail(PSF_EINVAL, "npix=%lld outside 1..2^31", (long long)npix);
+  return PSF_OK;
+}
+
+}  // namespace
+}  // namespace psf
+
 using namespace psf;
+
+extern "C" int psf_flux_scale(int32_t n_src, int64_t npix, const float* flux, const float* P, float* out,
+                              void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_flux(n_src, npix)) != PSF_OK) return st;
+  if (flux == nullptr || P == nullptr || out == nullptr) return fail(PSF_EINVAL, "flux, P or out is NULL");
+  if ((st = check_device()) != PSF_OK) return st;
+  hipLaunchKernelGGL(k_flux_scale, dim3(static_cast<unsigned>((npix + 255) / 256), n_src), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), flux, P, npix, out);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_flux_scale launch");
+}
+
+extern "C" int psf_flux_backward(int32_t n_src, int64_t npix, const float* flux, const float* P, const float* grad_out,
+                                 float* G, double* grad_flux, void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_flux(n_src, npix)) != PSF_OK) return st;
+  if (flux == nullptr || P == nullptr || grad_out == nullptr || G == nullptr || grad_flux == nullptr)
+    return fail(PSF_EINVAL, "a pointer argument is NULL");
+  if ((st = check_device()) != PSF_OK) return st;
+  hipLaunchKernelGGL(k_flux_backward, dim3(n_src), dim3(256), 0, static_cast<hipStream_t>(stream), flux, P, grad_out,
+                     npix, G, grad_flux);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_flux_backward launch");
+}
 
 extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, const psf_src* d_srcs,
                                   const float* G_all, int prec, double* grad_lm, void* ws, size_t ws_bytes,

@@ -240,3 +240,11 @@ def test_method2_clean_host_side_errors(L):
     st, _ = status_of(L.psf_clean_hogbom_method2, 128, FAKE, ctypes.byref(sq), FAKE, 5, 0.5, 0.0, 20.0, 1e6, 1.4e9,
                       FAKE, FAKE, FAKE, ctypes.byref(n), FAKE, 64, None)
     assert st == pk.PSF_EWORKSPACE
+
+
+def test_flux_entry_points_host_side_errors(L):
+    assert L.psf_flux_scale(0, 10, FAKE, FAKE, FAKE, None) == pk.PSF_EINVAL
+    assert L.psf_flux_scale(2, 0, FAKE, FAKE, FAKE, None) == pk.PSF_EINVAL
+    assert L.psf_flux_scale(2, 10, None, FAKE, FAKE, None) == pk.PSF_EINVAL
+    assert L.psf_flux_backward(2, 10, FAKE, FAKE, FAKE, FAKE, None, None) == pk.PSF_EINVAL
+    assert L.psf_flux_backward(70000, 10, FAKE, FAKE, FAKE, FAKE, FAKE, None) == pk.PSF_EINVAL
