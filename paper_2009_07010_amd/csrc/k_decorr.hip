@@ -50,6 +50,91 @@ __device__ __forceinline__ cf32 expi_turns_sample(double theta) {
   z.im = __builtin_amdgcn_sinf(x);
   return z;
 }
+
+// Channels per register chunk of bin_sums.
+constexpr int kChanChunk = 8;
+
+// Sums over one bin's samples: S = sum x e with e = exp(-2 pi i phi) and x
+// the sample's window weight (1 without windows), the window sums of the bin
+// along time (st) and channel (sc), and for the adjoint G_l = sum x g_l e and
+// G_m = sum x g_m e with g = d phi / d(l0, m0).  The bin's channels are taken
+// in chunks whose frequencies and channel windows sit in registers, so the
+// only memory reads per time row are its uvw (and time window), loaded one
+// row ahead.  Samples are summed time-major within a chunk.
+struct BinSums {
+  float sre, sim, glr, gli, gmr, gmi, st, sc;
+};
+
+template <bool kWin, bool kGrad>
+__device__ __forceinline__ BinSums bin_sums(const ObsView& o, const BinRef& r, double l0, double m0, double Lw,
+                                            double A_knu, double nu_k, double uc, double vc, double wc,
+                                            double l0_n0, double m0_n0) {
+#pragma clang fp contract(off)
+  BinSums s{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
+  const float* win_tb = kWin && o.win_t != nullptr ? o.win_t + static_cast<int64_t>(r.b) * o.n_t : nullptr;
+  const float* win_cb = kWin && o.win_c != nullptr ? o.win_c + static_cast<int64_t>(r.b) * o.n_ch : nullptr;
+  if constexpr (kWin) {
+    for (int c = r.c0; c < r.c1; ++c) s.sc += win_cb != nullptr ? win_cb[c] : 1.f;
+    for (int t = r.t0; t < r.t1; ++t) s.st += win_tb != nullptr ? win_tb[t] : 1.f;
+  }
+  for (int cb = r.c0; cb < r.c1; cb += kChanChunk) {
+    const int nch = min(kChanChunk, r.c1 - cb);
+    double nu[kChanChunk];
+    float xc[kChanChunk];
+#pragma unroll
+    for (int j = 0; j < kChanChunk; ++j) {
+      const int c = cb + min(j, nch - 1);  // clamped: always a channel of the bin
+      nu[j] = o.freq[c];
+      xc[j] = kWin && win_cb != nullptr ? win_cb[c] : 1.f;
+    }
+    double u = row[3 * r.t0], v = row[3 * r.t0 + 1], w = row[3 * r.t0 + 2];
+    float xt = kWin && win_tb != nullptr ? win_tb[r.t0] : 1.f;
+    for (int t = r.t0; t < r.t1; ++t) {
+      const int tn = min(t + 1, r.t1 - 1);
+      const double un = row[3 * tn], vn = row[3 * tn + 1], wn = row[3 * tn + 2];
+      const float xtn = kWin && win_tb != nullptr ? win_tb[tn] : 1.f;
+      const double A_t = u * l0 + v * m0 + w * Lw;
+#pragma unroll
+      for (int j = 0; j < kChanChunk; ++j) {
+        if (j < nch) {
+          const double nu_c = nu[j];
+          const double phi = (A_t * nu_c - A_knu) * kInvCLight;
+          const cf32 e = expi_turns_sample(-phi);
+          const float x = kWin ? xt * xc[j] : 1.f;
+          if constexpr (kWin) {
+            s.sre += x * e.re;
+            s.sim += x * e.im;
+          } else {
+            s.sre += e.re;
+            s.sim += e.im;
+          }
+          if constexpr (kGrad) {
+            const double du = (u * nu_c - uc * nu_k) * kInvCLight;
+            const double dv = (v * nu_c - vc * nu_k) * kInvCLight;
+            const double dw = (w * nu_c - wc * nu_k) * kInvCLight;
+            float gl = static_cast<float>(du - dw * l0_n0);
+            float gm = static_cast<float>(dv - dw * m0_n0);
+            if constexpr (kWin) {
+              gl = x * gl;
+              gm = x * gm;
+            }
+            // -2 pi i g e  =  2 pi g (e.im, -e.re); the 2 pi is applied by the caller
+            s.glr += gl * e.im;
+            s.gli -= gl * e.re;
+            s.gmr += gm * e.im;
+            s.gmi -= gm * e.re;
+          }
+        }
+      }
+      u = un;
+      v = vn;
+      w = wn;
+      xt = xtn;
+    }
+  }
+  return s;
+}
 }  // namespace
 
 // One thread per bin.  Writes any subset of: D, record (u', v', c = W D),
@@ -61,6 +146,7 @@ __device__ __forceinline__ cf32 expi_turns_sample(double theta) {
 // is read from device memory at dirs + y * dir_stride (l0, m0 as the first
 // two doubles) when dirs is given, and whose records start y * rec_stride
 // elements into rec_out and c_out.
+template <bool kGrad>
 __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0, double dl, double dm,
                                                 const double* __restrict__ dirs, int64_t dir_stride,
                                                 int64_t rec_stride,
@@ -90,7 +176,6 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
 
   float dre = 0.f, dim = 0.f;
   float dDl_re = 0.f, dDl_im = 0.f, dDm_re = 0.f, dDm_im = 0.f;
-  const bool grad = coef_out != nullptr && D_in == nullptr;
   if (D_in != nullptr) {
     const float2 d = D_in[k];
     dre = d.x;
@@ -98,84 +183,29 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   } else {
     const double A_k = uc * l0 + vc * m0 + wc * Lw;
     const double A_knu = A_k * nu_k;
-    float sre = 0.f, sim = 0.f;
-    float glr = 0.f, gli = 0.f, gmr = 0.f, gmi = 0.f;
-    const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
+    const double l0_n0 = l0 / n0, m0_n0 = m0 / n0;
+    float inv;
+    BinSums bs;
     if (o.win_t != nullptr || o.win_c != nullptr) {
       // Windowed averaging: sample weight x = win_t[b][t] win_c[b][c], the
       // mean normalised by the window's sum over the bin (D = 0 for a
       // window that sums to 0).  Separable, so the normaliser is the
       // product of the two axis sums.
-      const float* win_tb = o.win_t != nullptr ? o.win_t + static_cast<int64_t>(r.b) * o.n_t : nullptr;
-      const float* win_cb = o.win_c != nullptr ? o.win_c + static_cast<int64_t>(r.b) * o.n_ch : nullptr;
-      float st = 0.f, sc = 0.f;
-      for (int c = r.c0; c < r.c1; ++c) sc += win_cb != nullptr ? win_cb[c] : 1.f;
-      for (int t = r.t0; t < r.t1; ++t) {
-        const float xt = win_tb != nullptr ? win_tb[t] : 1.f;
-        st += xt;
-        const double u = row[3 * t + 0], v = row[3 * t + 1], w = row[3 * t + 2];
-        const double A_t = u * l0 + v * m0 + w * Lw;
-        for (int c = r.c0; c < r.c1; ++c) {
-          const float x = xt * (win_cb != nullptr ? win_cb[c] : 1.f);
-          const double nu = o.freq[c];
-          const double phi = (A_t * nu - A_knu) * kInvCLight;
-          const cf32 e = expi_turns_sample(-phi);
-          sre += x * e.re;
-          sim += x * e.im;
-          if (grad) {
-            const double du = (u * nu - uc * nu_k) * kInvCLight;
-            const double dv = (v * nu - vc * nu_k) * kInvCLight;
-            const double dw = (w * nu - wc * nu_k) * kInvCLight;
-            const float gl = x * static_cast<float>(du - dw * l0 / n0);
-            const float gm = x * static_cast<float>(dv - dw * m0 / n0);
-            glr += gl * e.im; gli -= gl * e.re;
-            gmr += gm * e.im; gmi -= gm * e.re;
-          }
-        }
-      }
-      const float norm = st * sc;
-      const float inv = norm != 0.f ? 1.0f / norm : 0.f;
-      dre = sre * inv;
-      dim = sim * inv;
-      if (grad) {
-        const float s = 6.283185307179586f * inv;
-        dDl_re = glr * s;
-        dDl_im = gli * s;
-        dDm_re = gmr * s;
-        dDm_im = gmi * s;
-      }
+      bs = bin_sums<true, kGrad>(o, r, l0, m0, Lw, A_knu, nu_k, uc, vc, wc, l0_n0, m0_n0);
+      const float norm = bs.st * bs.sc;
+      inv = norm != 0.f ? 1.0f / norm : 0.f;
     } else {
-    for (int t = r.t0; t < r.t1; ++t) {
-      const double u = row[3 * t + 0], v = row[3 * t + 1], w = row[3 * t + 2];
-      const double A_t = u * l0 + v * m0 + w * Lw;
-      for (int c = r.c0; c < r.c1; ++c) {
-        const double nu = o.freq[c];
-        const double phi = (A_t * nu - A_knu) * kInvCLight;
-        const cf32 e = expi_turns_sample(-phi);
-        sre += e.re;
-        sim += e.im;
-        if (grad) {
-          const double du = (u * nu - uc * nu_k) * kInvCLight;
-          const double dv = (v * nu - vc * nu_k) * kInvCLight;
-          const double dw = (w * nu - wc * nu_k) * kInvCLight;
-          const float gl = static_cast<float>(du - dw * l0 / n0);
-          const float gm = static_cast<float>(dv - dw * m0 / n0);
-          // -2 pi i g e  =  2 pi g (e.im, -e.re)
-          glr += gl * e.im; gli -= gl * e.re;
-          gmr += gm * e.im; gmi -= gm * e.re;
-        }
-      }
+      bs = bin_sums<false, kGrad>(o, r, l0, m0, Lw, A_knu, nu_k, uc, vc, wc, l0_n0, m0_n0);
+      inv = 1.0f / static_cast<float>((r.t1 - r.t0) * (r.c1 - r.c0));
     }
-    const float inv_n = 1.0f / static_cast<float>((r.t1 - r.t0) * (r.c1 - r.c0));
-    dre = sre * inv_n;
-    dim = sim * inv_n;
-    if (grad) {
-      const float s = 6.283185307179586f * inv_n;
-      dDl_re = glr * s;
-      dDl_im = gli * s;
-      dDm_re = gmr * s;
-      dDm_im = gmi * s;
-    }
+    dre = bs.sre * inv;
+    dim = bs.sim * inv;
+    if constexpr (kGrad) {
+      const float sc = 6.283185307179586f * inv;
+      dDl_re = bs.glr * sc;
+      dDl_im = bs.gli * sc;
+      dDm_re = bs.gmr * sc;
+      dDm_im = bs.gmi * sc;
     }
   }
   if (D_out != nullptr) D_out[k] = make_float2(dre, dim);
@@ -194,7 +224,7 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
   const float W = o.W[k];
   const float cre = W * dre, cim = W * dim;
   if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
-  if (grad) {
+  if (kGrad && coef_out != nullptr && D_in == nullptr) {
     // 2 pi i c t = 2 pi t (-Im c, Re c) for real t.  All five vectors are
     // scaled by kAdjointScale (a power of two, exact) so that they stay in
     // the FP16 range of the split-FP16 contraction (|2 pi u' c| reaches a
@@ -219,8 +249,12 @@ hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, doub
                          float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
-  hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0, dl, dm,
-                     nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
+  if (coef_out != nullptr && D_in == nullptr)
+    hipLaunchKernelGGL(k_decorr<true>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0,
+                       dl, dm, nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
+  else
+    hipLaunchKernelGGL(k_decorr<false>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0,
+                       dl, dm, nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, nullptr);
   return hipGetLastError();
 }
 
@@ -228,7 +262,7 @@ hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t d
                                  BinRec* rec_out, float2* c_out, int64_t rec_stride, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
-  hipLaunchKernelGGL(k_decorr, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(n_src)), dim3(threads), 0,
+  hipLaunchKernelGGL(k_decorr<false>, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(n_src)), dim3(threads), 0,
                      stream, o, 0.0, 0.0, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, nullptr, rec_out, c_out,
                      nullptr);
   return hipGetLastError();

@@ -129,7 +129,7 @@ def test_windowed_backward_config1(pk, prec):
     loss = ((out.double() - torch.as_tensor(np.stack(T), device="cuda").double()) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
-    assert abs(float(loss) - L_ref) <= 1e-3 * L_ref
+    assert abs(float(loss.detach()) - L_ref) <= 1e-3 * L_ref
     g_lm, g_f = lm.grad.numpy(), f.grad.double().cpu().numpy()
     for s in range(len(srcs)):
         err = np.max(np.abs(g_lm[s] - g_ref[s])) / np.max(np.abs(g_ref[s]))
