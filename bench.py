@@ -110,8 +110,15 @@ def time_method1(pk, torch, dobs, src, prec, ws, reps=10):
     exact_ms = timed(lambda: pk.decorr(dobs, src.l0, src.m0, out=D))
     Dc = pk.decorr_sinc(dobs, src.l0, src.m0)
     psf_ms = timed(lambda: pk.patch(dobs, src, prec=prec, D=Dc, workspace=ws))
+    # exact factors: every uvw row (24 B), every time-bin centre (24 B) and
+    # D (8 B per bin) once; every sample's phase is evaluated
+    exact_bytes = 24.0 * dobs.n_bl * dobs.n_t + 24.0 * dobs.n_tb + 8.0 * dobs.K
+    samples = float(dobs.n_bl) * dobs.n_t * dobs.n_ch
     return {"decorr_sinc_ms": sinc_ms, "decorr_exact_ms": exact_ms,
             "decorr_sinc_GBps": 80.0 * dobs.K / (sinc_ms * 1e-3) / 1e9,
+            "decorr_exact_GBps": exact_bytes / (exact_ms * 1e-3) / 1e9,
+            "decorr_exact_hbm_frac": exact_bytes / (exact_ms * 1e-3) / 8.0e12,
+            "decorr_exact_samples_per_s": samples / (exact_ms * 1e-3),
             "psf_from_sinc_ms": psf_ms}
 
 

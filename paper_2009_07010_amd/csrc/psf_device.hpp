@@ -46,14 +46,25 @@ __device__ __forceinline__ cf32 expi_turns(double theta) {
   return z;
 }
 
-// Index of the baseline that owns bin k: largest b with koff[b] <= k.
+// Index of the baseline that owns bin k: largest b with koff[b] <= k.  The
+// wave's first active lane is searched for by bisection in uniform control
+// flow (scalar loads, no dependent vector loads); every lane then steps from
+// there to its own baseline, which for the consecutive bins of a wave is
+// usually no step at all.  The result stays in [0, n_bl - 1] whatever koff
+// holds.
 __device__ __forceinline__ int find_baseline(const int64_t* __restrict__ koff, int n_bl, int64_t k) {
-  int lo = 0, hi = n_bl;  // koff[lo] <= k < koff[hi]
+  const int64_t k0 = static_cast<int64_t>(
+      (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(k >> 32)))) << 32) |
+      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(k & 0xffffffff))));
+  int lo = 0, hi = n_bl;  // koff[lo] <= k0 < koff[hi]
   while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (koff[mid] <= k) lo = mid; else hi = mid;
+    const int mid = (lo + hi) >> 1;
+    if (koff[mid] <= k0) lo = mid; else hi = mid;
   }
-  return lo;
+  int b = lo;
+  while (b + 1 < n_bl && koff[b + 1] <= k) ++b;
+  while (b > 0 && koff[b] > k) --b;
+  return b;
 }
 
 // Where bin k lives: baseline, sample and channel ranges, time-bin row.
@@ -73,7 +84,8 @@ __device__ __forceinline__ BinRef locate_bin(const int64_t* __restrict__ koff,
   const int nt = bl_bin[2 * r.b], nc = bl_bin[2 * r.b + 1];
   const int n_fb = (n_ch + nc - 1) / nc;
   const int64_t local = k - koff[r.b];
-  const int T = static_cast<int>(local / n_fb);
+  // 32-bit division where the bin's index within its baseline allows
+  const int T = local <= 0x7fffffff ? static_cast<int>(local) / n_fb : static_cast<int>(local / n_fb);
   const int F = static_cast<int>(local - static_cast<int64_t>(T) * n_fb);
   r.t0 = T * nt;
   r.t1 = min(n_t, r.t0 + nt);
