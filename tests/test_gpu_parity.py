@@ -156,6 +156,23 @@ def test_single_sample_bins_and_phase_centre():
     assert np.all(D0 == 1.0 + 0.0j)
 
 
+
+@pytest.mark.parametrize("nt,nc", [(6, 3), (3, 3)])
+def test_waves_spanning_many_baselines(nt, nc):
+    """One or two bins per baseline (78 baselines): every lane of a wave
+    belongs to a different baseline than its neighbours, so each lane steps
+    from the wave's bisection result to its own baseline."""
+    obs = ps.tiny_random(35, n_ant=13, n_t=6, n_ch=3, nt=nt, nc=nc, radius_m=3000.0)
+    assert obs.K == (6 // nt) * (3 // nc) * 78
+    src = ps.Source.centred(0.011, -0.017, 33, 2 * ps.ARCSEC)
+    D = orc.decorr(obs, src.l0, src.m0)
+    dobs = pk.DeviceObservation(obs)
+    Dg = pk.decorr(dobs, src.l0, src.m0).cpu().numpy()
+    assert np.max(np.abs(Dg - D)) < 2e-6
+    P = orc.patch_factored(obs, src, D)
+    for prec in ACCURATE:
+        assert orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0] < TOL, prec
+
 def test_zero_weights_give_zero_patch():
     obs = ps.tiny_random(34, n_ant=4, n_t=9, n_ch=3, nt=3, nc=2)
     obs.W[:] = 0.0
