@@ -86,3 +86,18 @@ def test_wide_bin_gradient(pk, windowed):
         ferr = abs(g_f[s] - gf_ref[s]) / fscale[s]
         print(f"wide bins windowed={windowed} grad src{s}: dir {err:.2e} flux {ferr:.2e}", flush=True)
         assert err <= 1e-4 and ferr <= 1e-4
+
+
+def test_wide_bin_batched(pk):
+    """The batched path forms its records with the several-source launch of
+    the decorrelation: mixed patch sizes on the wide bins, windowed."""
+    obs = _obs(True, 1.38e9, 1.42e9)
+    cell = 2.0 * ps.ARCSEC
+    srcs = [ps.Source.centred(l0, m0, n, cell)
+            for l0, m0, n in ((0.0021, -0.0013, 65), (-0.0017, 0.0009, 33), (0.0004, 0.0019, 129))]
+    parts = pk.split_patches(pk.patch_batched(pk.DeviceObservation(obs), srcs, prec="split_bf16"), srcs)
+    torch.cuda.synchronize()
+    for s, P in zip(srcs, parts):
+        err = orc.peak_normalised_error(P.double().cpu().numpy(), orc.patch_factored(obs, s))[0]
+        print(f"wide bins batched {s.nl}: {err:.2e}", flush=True)
+        assert err < TOL
