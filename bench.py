@@ -143,6 +143,7 @@ def time_windows_fullw(pk, torch, ps, obs, dobs, src, prec, ws, reps=5):
     del dw
     out = torch.empty((src.nl, src.nm), dtype=torch.float32, device="cuda")
     n_terms = pk.patch_fullw(dobs, src, prec=prec, out=out, workspace=ws)[1]
+    torch.cuda.synchronize()  # the warm-up's contractions are still queued when it returns
     t0 = time.perf_counter()
     for _ in range(reps):
         pk.patch_fullw(dobs, src, prec=prec, out=out, workspace=ws)
