@@ -74,10 +74,6 @@ __device__ __forceinline__ BinSums bin_sums(const ObsView& o, const BinRef& r, d
   const double* row = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
   const float* win_tb = kWin && o.win_t != nullptr ? o.win_t + static_cast<int64_t>(r.b) * o.n_t : nullptr;
   const float* win_cb = kWin && o.win_c != nullptr ? o.win_c + static_cast<int64_t>(r.b) * o.n_ch : nullptr;
-  if constexpr (kWin) {
-    for (int c = r.c0; c < r.c1; ++c) s.sc += win_cb != nullptr ? win_cb[c] : 1.f;
-    for (int t = r.t0; t < r.t1; ++t) s.st += win_tb != nullptr ? win_tb[t] : 1.f;
-  }
   for (int cb = r.c0; cb < r.c1; cb += kChanChunk) {
     const int nch = min(kChanChunk, r.c1 - cb);
     double nu[kChanChunk];
@@ -88,12 +84,19 @@ __device__ __forceinline__ BinSums bin_sums(const ObsView& o, const BinRef& r, d
       nu[j] = o.freq[c];
       xc[j] = kWin && win_cb != nullptr ? win_cb[c] : 1.f;
     }
+    if constexpr (kWin) {
+      // the window sums in channel and time order, from the loaded weights
+#pragma unroll
+      for (int j = 0; j < kChanChunk; ++j)
+        if (j < nch) s.sc += xc[j];
+    }
     double u = row[3 * r.t0], v = row[3 * r.t0 + 1], w = row[3 * r.t0 + 2];
     float xt = kWin && win_tb != nullptr ? win_tb[r.t0] : 1.f;
     for (int t = r.t0; t < r.t1; ++t) {
       const int tn = min(t + 1, r.t1 - 1);
       const double un = row[3 * tn], vn = row[3 * tn + 1], wn = row[3 * tn + 2];
       const float xtn = kWin && win_tb != nullptr ? win_tb[tn] : 1.f;
+      if (kWin && cb == r.c0) s.st += xt;
       const double A_t = u * l0 + v * m0 + w * Lw;
 #pragma unroll
       for (int j = 0; j < kChanChunk; ++j) {
