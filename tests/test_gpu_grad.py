@@ -44,7 +44,7 @@ def _gpu_loss_grad(pk, obs, srcs, fluxes, targets, prec):
     loss = ((out.double() - T.double()) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), lm.grad.numpy().copy(), f.grad.double().cpu().numpy()
+    return float(loss.detach()), lm.grad.numpy().copy(), f.grad.double().cpu().numpy()
 
 
 def _check(g_lm, g_f, ref_lm, ref_f, label, flux_scale=None):
