@@ -194,16 +194,24 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
         }
       }
     }
+    // Along a lane's 8 consecutive columns the factors follow the real
+    // three-term recurrence z+ = 2 cos(t) z - z- of the column step e^{it}
+    // (two fused multiply-adds per column); the jump to the next k-step's
+    // first column, and its predecessor, are complex products.
     const cf32 s1 = expi_turns(vp * a.dm), s25 = expi_turns(vp * (25.0 * a.dm));
+    const cf32 s24 = cmul(s25, conj(s1));
+    const float tc = 2.0f * s1.re;
+    cf32 zp = cmul(zb, conj(s1));  // the column before zb
     for (int ks = 0; ks < (PREC == kFP32 ? 0 : a.nks); ++ks) {
       // b and y b at columns 32 ks + 8 jg + t, t = 0..7: re, im, y re, y im
       v4u bh[4], bl[4];
 #pragma unroll
       for (int t = 0; t < 8; t += 2) {
         const cf32 z0 = zb;
-        zb = cmul(zb, s1);
-        const cf32 z1 = zb;
-        if (t < 6) zb = cmul(zb, s1);
+        const cf32 z1 = {__builtin_fmaf(tc, z0.re, -zp.re), __builtin_fmaf(tc, z0.im, -zp.im)};
+        zp = z1;
+        zb = z1;
+        if (t < 6) zb = {__builtin_fmaf(tc, z1.re, -z0.re), __builtin_fmaf(tc, z1.im, -z0.im)};
         const float y0 = ys0 + static_cast<float>(32 * ks + t) * ystep, y1 = y0 + ystep;
         uint32_t h, w;
         split2<PREC>(z0.re, z1.re, h, w);
@@ -219,6 +227,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
         bh[3][t / 2] = h;
         bl[3][t / 2] = w;
       }
+      zp = cmul(zb, s24);  // column 32 (ks + 1) + 8 jg - 1
       zb = cmul(zb, s25);  // column 32 ks + 8 jg + 7 -> 32 (ks + 1) + 8 jg
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
