@@ -704,8 +704,19 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
   const float* q = p.partial + tile_first_elem(t, ti, tj) + (static_cast<int64_t>(blk) * 64 + cc + 16 * (rr >> 2)) * 4 +
                    (rr & 3);
   const int64_t slab = slab_elems(t, r, c);
+  // slices added in order; 16 loads are issued before their adds so that
+  // their latencies overlap (same sum, bit for bit)
+  const int nsl = t.ns[r][c];
   float sum = 0.f;
-  for (int n = 0; n < t.ns[r][c]; ++n) sum += q[n * slab];
+  int n = 0;
+  for (; n + 16 <= nsl; n += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = q[(n + u) * slab];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += v[u];
+  }
+  for (; n < nsl; ++n) sum += q[n * slab];
   p.P[idx] = 2.0f * sum;
 }
 
