@@ -36,20 +36,11 @@
 namespace psf {
 
 namespace {
-// exp(2 pi i theta) for the per-sample factors: the argument reduced to
-// [-1/2, 1/2] turns in FP64, then the hardware sine and cosine, which take
-// their argument in turns (about 4e-7 absolute error; D_k stays within FP32
-// rounding of the FP64 mean).  sin(0) = 0 and cos(0) = 1 exactly, so
-// D_k = 1 remains exact where every phase difference is 0.  The 16-pixel
-// step factors of the records, raised to powers by the contraction's
-// recurrence, keep the polynomial form.
-__device__ __forceinline__ cf32 expi_turns_sample(double theta) {
-  const float x = static_cast<float>(theta - rint(theta));
-  cf32 z;
-  z.re = __builtin_amdgcn_cosf(x);
-  z.im = __builtin_amdgcn_sinf(x);
-  return z;
-}
+// The per-sample factors use the hardware sine and cosine (expi_turns_hw):
+// D_k stays within FP32 rounding of the FP64 mean, and D_k = 1 remains exact
+// where every phase difference is 0.  The 16-pixel step factors of the
+// records, raised to powers by the contraction's recurrence, keep the
+// polynomial form.
 
 // Channels per register chunk of bin_sums.
 constexpr int kChanChunk = 8;
@@ -103,7 +94,7 @@ __device__ __forceinline__ BinSums bin_sums(const ObsView& o, const BinRef& r, d
         if (j < nch) {
           const double nu_c = nu[j];
           const double phi = (A_t * nu_c - A_knu) * kInvCLight;
-          const cf32 e = expi_turns_sample(-phi);
+          const cf32 e = expi_turns_hw(-phi);
           const float x = kWin ? xt * xc[j] : 1.f;
           if constexpr (kWin) {
             s.sre += x * e.re;

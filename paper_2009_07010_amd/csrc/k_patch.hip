@@ -221,7 +221,8 @@ constexpr bool wave_shapes_ok() {
 // waves 4-7 write B (tile columns), so each SIMD (waves w and w + 4) holds
 // one of each.  Thread (visibility gv, class rc = 4 (w mod 4) + lane / 16)
 // writes rows rc, rc + 16, ... of its axis for every chunk: one FP64-reduced
-// seed at row rc and the bin's 16-row step (formed once per bin with the
+// seed at row rc (hardware sine and cosine: used once, its 4e-7 error stays
+// far below the split's rounding) and the bin's 16-row step (formed once per bin with the
 // records), then the real three-term recurrence z+ = 2 cos(t) z - z- of a
 // unit step e^{it} along the rows: two fused multiply-adds per row instead
 // of a complex product.  A rounding error made at one row reaches row n
@@ -286,7 +287,7 @@ struct Gen {
   // Seed and step of the chunk held in ring slot 0, to be written into
   // buffer buf (the step comes with the record).
   __device__ __forceinline__ void begin(lds_t* smem, int buf) {
-    z = expi_turns(rf[0] * pos0);
+    z = expi_turns_hw(rf[0] * pos0);  // the seed is used once: hardware sin/cos
     cf32 zs = rst[0];
     if (IS_A) {
       const cf32 cc = rok[0] ? rcc[0] : cf32{0.f, 0.f};

@@ -21,6 +21,19 @@ __device__ __forceinline__ cf32 cmul(cf32 a, cf32 b) {
 }
 __device__ __forceinline__ cf32 conj(cf32 a) { return {a.re, -a.im}; }
 
+// exp(2 pi i theta) for theta in turns, with the hardware sine and cosine:
+// the argument reduced to [-1/2, 1/2] turns in FP64, then v_sin / v_cos,
+// which take turns (about 4e-7 absolute error).  sin(0) = 0 and cos(0) = 1
+// exactly.  For values used once (a sample's phase factor, a row seed); a
+// factor raised to powers uses the polynomial form below.
+__device__ __forceinline__ cf32 expi_turns_hw(double theta) {
+  const float x = static_cast<float>(theta - rint(theta));
+  cf32 z;
+  z.re = __builtin_amdgcn_cosf(x);
+  z.im = __builtin_amdgcn_sinf(x);
+  return z;
+}
+
 // exp(2 pi i theta) for theta in turns.
 //
 // FP64 step: q = nearest quarter turn, r = theta - q/4 with |r| <= 1/8 turn
