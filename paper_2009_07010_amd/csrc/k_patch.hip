@@ -229,8 +229,10 @@ constexpr bool wave_shapes_ok() {
 // scaled by at most n, so over the 17 rows of the widest tile an element
 // stays within ~1e-5 (17^2 / 2 FP32 roundings), and far closer after the
 // sum over visibilities.  A row class is constant mod 8, so the thread's
-// swizzle is constant.  Per-bin records are fetched three chunks ahead into
-// a shift register.
+// swizzle is constant.  Per-bin records are fetched one chunk ahead (the
+// record stream is cache-resident and the loads issue early in the chunk;
+// deeper prefetch rings measured slower: their register shifts cost more
+// than the latency they hide).
 template <int PREC, int TBI, int TBJ, bool IS_A>
 struct Gen {
   using G = TileGeom<PREC, TBI, TBJ>;
@@ -238,7 +240,7 @@ struct Gen {
   static constexpr int GSTRIDE = IS_A ? G::GA : G::GB;
   static constexpr int GOFF = IS_A ? 0 : G::NPL * G::APL;
   static constexpr int GLO = IS_A ? G::APL : G::BPL;
-  static constexpr int P = 3;  // chunks of records held ahead
+  static constexpr int P = 1;  // chunks of records held ahead
 
   int gv, rc;
   double pos0;
