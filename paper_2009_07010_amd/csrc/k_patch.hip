@@ -229,10 +229,9 @@ constexpr bool wave_shapes_ok() {
 // scaled by at most n, so over the 17 rows of the widest tile an element
 // stays within ~1e-5 (17^2 / 2 FP32 roundings), and far closer after the
 // sum over visibilities.  A row class is constant mod 8, so the thread's
-// swizzle is constant.  Per-bin records are fetched one chunk ahead (the
-// record stream is cache-resident and the loads issue early in the chunk;
-// deeper prefetch rings measured slower: their register shifts cost more
-// than the latency they hide).
+// swizzle is constant.  Per-bin records are fetched one chunk ahead:
+// deeper prefetch rings measured slower, their register shifts costing more
+// vector issue slots than the latency they hide.
 template <int PREC, int TBI, int TBJ, bool IS_A>
 struct Gen {
   using G = TileGeom<PREC, TBI, TBJ>;
