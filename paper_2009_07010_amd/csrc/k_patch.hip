@@ -223,12 +223,15 @@ constexpr bool wave_shapes_ok() {
 // writes rows rc, rc + 16, ... of its axis for every chunk: one FP64-reduced
 // seed at row rc (hardware sine and cosine: used once, its 4e-7 error stays
 // far below the split's rounding) and the bin's 16-row step (formed once per bin with the
-// records), then the real three-term recurrence z+ = 2 cos(t) z - z- of a
-// unit step e^{it} along the rows: two fused multiply-adds per row instead
-// of a complex product.  A rounding error made at one row reaches row n
-// scaled by at most n, so over the 17 rows of the widest tile an element
-// stays within ~1e-5 (17^2 / 2 FP32 roundings), and far closer after the
-// sum over visibilities.  A row class is constant mod 8, so the thread's
+// records), then along the rows: for the split forms the real three-term
+// recurrence z+ = 2 cos(t) z - z- of a unit step e^{it} (two fused
+// multiply-adds per row instead of a complex product).  Its error grows
+// with the row count and with the conditioning of the rounded 2 cos(t) near
+// small steps: at most 1.3e-5 of an element over 17 rows (a step near 1e-3
+// rad), against 9e-7 for the complex product and about 8e-6 for the split
+// representation itself; across visibilities these errors are incoherent,
+// and the patch errors are unchanged.  The FP32 form, the precision
+// baseline, keeps the complex product.  A row class is constant mod 8, so the thread's
 // swizzle is constant.  Per-bin records are fetched one chunk ahead:
 // deeper prefetch rings measured slower, their register shifts costing more
 // vector issue slots than the latency they hide.
@@ -250,8 +253,8 @@ struct Gen {
   cf32 rst[P];    // 16-row step
   cf32 rcc[P];    // W D (A)
   bool rok[P];
-  cf32 z, zp;  // current and previous row's factor
-  float tc;    // 2 cos t of the 16-row step
+  cf32 z, zp;  // current and previous row's factor (zp: the step itself in FP32)
+  float tc;    // 2 cos t of the 16-row step (split forms)
   lds_t* plane;
 
   __device__ __forceinline__ Gen(const TileArgs& a, int wave, int bi0, int bj0, int64_t kb_, int64_t ke_) {
@@ -295,8 +298,12 @@ struct Gen {
       z = conj(cmul(cc, z));
       zs = conj(zs);
     }
-    zp = cmul(z, conj(zs));  // the row before the seed
-    tc = 2.0f * zs.re;
+    if constexpr (PREC == kFP32) {
+      zp = zs;
+    } else {
+      zp = cmul(z, conj(zs));  // the row before the seed
+      tc = 2.0f * zs.re;
+    }
     plane = smem + buf * G::BUF + GOFF;
   }
   // Rows [q0, q1) of the current chunk (q0, q1 fold to constants once the
@@ -306,9 +313,13 @@ struct Gen {
     for (int q = 0; q < R; ++q) {
       if (q < q0 || q >= q1) continue;
       store_operand<PREC>(plane, GLO, GSTRIDE, rc + 16 * q, gv, z);
-      const cf32 zn = {__builtin_fmaf(tc, z.re, -zp.re), __builtin_fmaf(tc, z.im, -zp.im)};
-      zp = z;
-      z = zn;
+      if constexpr (PREC == kFP32) {
+        z = cmul(z, zp);
+      } else {
+        const cf32 zn = {__builtin_fmaf(tc, z.re, -zp.re), __builtin_fmaf(tc, z.im, -zp.im)};
+        zp = z;
+        z = zn;
+      }
     }
   }
   // Shift the ring by one chunk and fetch chunk n into its last slot.
