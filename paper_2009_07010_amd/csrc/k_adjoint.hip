@@ -196,8 +196,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
     }
     // Along a lane's 8 consecutive columns the factors follow the real
     // three-term recurrence z+ = 2 cos(t) z - z- of the column step e^{it}
-    // (two fused multiply-adds per column); the jump to the next k-step's
-    // first column, and its predecessor, are complex products.
+    // (two fused multiply-adds per column; over 8 columns an element stays
+    // within 3e-6, under the split representation's rounding); the jump to
+    // the next k-step's first column, and its predecessor, are complex
+    // products.
     const cf32 s1 = expi_turns(vp * a.dm), s25 = expi_turns(vp * (25.0 * a.dm));
     const cf32 s24 = cmul(s25, conj(s1));
     const float tc = 2.0f * s1.re;
