@@ -173,6 +173,21 @@ def test_waves_spanning_many_baselines(nt, nc):
     for prec in ACCURATE:
         assert orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0] < TOL, prec
 
+
+def test_small_row_steps():
+    """Baselines of a few metres at a 0.05 arcsec cell: the 16-row step of
+    every phase factor is 1e-4 to 1e-3 rad, where the split forms' row
+    recurrence is least accurate per element (its rounded 2 cos t is
+    ill-conditioned there), for every visibility at once."""
+    obs = ps.tiny_random(51, n_ant=8, n_t=60, n_ch=4, nt=3, nc=2, radius_m=10.0, dt=60.0)
+    src = ps.Source.centred(0.003, -0.002, 257, 0.05 * ps.ARCSEC)
+    P = orc.patch_factored(obs, src)
+    dobs = pk.DeviceObservation(obs)
+    for prec in ACCURATE:
+        err = orc.peak_normalised_error(gpu_patch(dobs, src, prec), P)[0]
+        print(f"small row steps {prec}: {err:.2e}", flush=True)
+        assert err < TOL, (prec, err)
+
 def test_zero_weights_give_zero_patch():
     obs = ps.tiny_random(34, n_ant=4, n_t=9, n_ch=3, nt=3, nc=2)
     obs.W[:] = 0.0
