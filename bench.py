@@ -2,17 +2,23 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec split_bf16]
 
-One step = one PSF of the MeerKAT-shaped workload (64 antennas, 2016
-baselines, 3600 x 2 s, 32 channels over 1.3-1.5 GHz, 20 s x 4 channel bins:
-K = 5,806,080 averaged visibilities; one source at 1 deg; 257 x 257 patch at
-1.5"): decorrelation factors, phase factors, contraction and finalise, all
-inside one psf_patch call on device-resident inputs.  The value is
-vis.pixel terms/s (K x 257^2 one-sided terms per PSF).
+Headline workload: baseline-dependent averaging of a MeerKAT-shaped array
+(64 antennas, 2016 baselines, 14400 x 1 s, 64 channels over 1.3-1.5 GHz,
+per-baseline bins of floor(B_max/|b|) clamped to 1-64 samples x 1-8
+channels: K = 265,127,960 averaged visibilities) with 256 sources at
+0.05-3 deg whose patches are 65, 129 or 257 pixels square at 1.5".  One
+step = one replay of a captured HIP graph holding one psf_patch_batched
+call over 16 of the sources (decorrelation, phase factors, contraction
+and finalise of each); steps cycle through the 16 slices, so 16 steps
+cover all 256 sources.  The value is vis.pixel terms/s (K x nl x nm
+one-sided terms per PSF) over the timed steps.
 
-Printed: one JSON line with the headline (split-BF16 unless --prec says
-otherwise), the same workload in plain FP32 for comparison, the roofline of
-the contraction kernel measured with HIP events on its launch stream, and
-the FP64 CPU reference timed on a bounded sample on this host.
+Also printed, as keyed sub-entries: one PSF of the uniform-bin workload
+(K = 5.8M, 257^2) in split-BF16 and plain FP32; the precision workload
+(K = 23.2M, 64 sources of 257^2) in split-BF16, split-FP16 and FP32; the
+roofline of the contraction kernel from HIP events on its launch stream;
+the paper's two approximations, CLEAN, windows, exact w, the adjoint; and
+the FP64 CPU reference timed on a bounded sample of the headline workload.
 """
 import argparse
 import json
@@ -24,9 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "plain_bf16": 2516.6, "fp32": 157.3}
-# executed matrix-core flops per useful one-sided term: 2 real MACs (Re*Re and
-# Im*Im) per term, times 3 products for the split forms
-FLOPS_PER_TERM = {"split_bf16": 12.0, "split_fp16": 12.0, "plain_bf16": 4.0, "fp32": 4.0}
+# algorithmic work per useful one-sided term: 2 real multiply-adds
+# (Re c a Re b - Im c a Im b), 4 flops, whatever the arithmetic
+ALG_FLOPS_PER_TERM = 4.0
+# matrix-core products per term product: 3 for the split forms (hi hi, hi lo, lo hi)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "plain_bf16": 1, "fp32": 1}
 DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "plain_bf16": "bf16", "fp32": "f32"}
 
 
@@ -34,14 +42,17 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="split_bf16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baselines", type=int, default=512,
-                    help="baselines in the CPU-reference sample")
+    ap.add_argument("--cpu-baselines", type=int, default=48,
+                    help="baselines of the headline workload in the CPU-reference sample")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="if > 0: only run this many steps of --prec (for rocprofv3) and print nothing else")
+                    help="if > 0: only run this many headline steps of --prec (for rocprofv3) and print "
+                         "nothing else")
+    ap.add_argument("--profile-workload", default="bda256", choices=["bda256", "meerkat257"],
+                    help="what --profile-steps runs: headline graph replays or single uniform-bin PSFs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="if > 0: only copy a buffer of this many MiB a few times (calibrates the HBM "
                          "byte counters against a plain copy kernel) and print nothing else")
@@ -228,8 +239,163 @@ def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
             "method2_ms_per_cycle": dt2 / max(1, len(comps2)) * 1e3}
 
 
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_pixels(names):
+    """Stored FP64 oracle values at sampled pixels: {source index: (i, j,
+    P_ij, peak)} from the listed golden files that exist."""
+    import numpy as np
+    out = {}
+    for n in names:
+        f = os.path.join(GOLD, n)
+        if not os.path.exists(f):
+            continue
+        rows = np.load(f)
+        for i in np.unique(rows[:, 0]).astype(int):
+            sel = rows[:, 0] == i
+            out[int(i)] = (rows[sel, 1].astype(int), rows[sel, 2].astype(int), rows[sel, 3], rows[sel, 4][0])
+    return out
+
+
+def headline_bda(pk, torch, ps, obs, srcs, prec, steps, warmup, ws, per_slice=16):
+    """One graph per 16-source slice of the headline workload, each holding
+    one psf_patch_batched call; `steps` replays cycling through the slices
+    are timed.  Returns the line's timing fields, the roofline of the
+    contraction kernel from an eager pass over every slice with HIP events
+    on its launch stream, and the error of the timed output at the stored
+    oracle pixels."""
+    import numpy as np
+    dobs = pk.DeviceObservation(obs)
+    slices = [srcs[i:i + per_slice] for i in range(0, len(srcs), per_slice)]
+    need = max(pk.workspace_bytes(dobs, sl, prec) for sl in slices)
+    ws.get(need)
+    # load every tile family's kernels once, outside capture
+    first = []
+    for n in sorted({s.nl for s in srcs}):
+        first.append(next(s for s in srcs if s.nl == n))
+    pk.patch_batched(dobs, first, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    graphs, outs, terms = [], [], []
+    for sl in slices:
+        _, d = pk.device_sources(sl, dobs.device)
+        out = torch.empty(sum(s.nl * s.nm for s in sl), dtype=torch.float32, device="cuda")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            pk.patch_batched(dobs, sl, prec=prec, out=out, workspace=ws, d_srcs=d)
+        graphs.append((g, d))
+        outs.append(out)
+        terms.append(float(dobs.K) * sum(s.nl * s.nm for s in sl))
+    torch.cuda.synchronize()
+    for w in range(warmup):
+        graphs[w % len(graphs)][0].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0.0
+    for st in range(steps):
+        q = st % len(graphs)
+        graphs[q][0].replay()
+        done += terms[q]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"headline: {steps} replays in {wall:.1f} s", file=sys.stderr, flush=True)
+    # error of what the timed replays wrote, at the stored oracle pixels
+    gold = golden_pixels(["config5_seed0_pixels.npy", "config5_seed0_far_pixels.npy"])
+    errs = {}
+    for i, (ii, jj, ref, peak) in sorted(gold.items()):
+        q, r = divmod(i, per_slice)
+        if q >= min(steps, len(graphs)) and q >= warmup:
+            continue
+        P = pk.split_patches(outs[q], slices[q])[r].cpu().numpy().astype(np.float64)
+        errs[str(i)] = float(np.max(np.abs(P[ii, jj] - ref)) / abs(peak))
+    # the contraction kernel's launches, timed with events on its stream
+    pk.psf_timing_read()
+    pk.psf_timing_enable(True)
+    t1 = time.perf_counter()
+    for sl in slices:
+        pk.patch_batched(dobs, sl, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t1
+    kms, nk = pk.psf_timing_read()
+    pk.psf_timing_enable(False)
+    all_terms = float(sum(terms))
+    del graphs, outs, dobs
+    torch.cuda.empty_cache()
+    return {"ms_per_step": wall / steps * 1e3, "terms_per_s": done / wall,
+            "psfs_per_s": steps * per_slice / wall, "graph_replays": steps,
+            "eager_all_256_s": eager_s, "kernel_ms_total": kms, "kernel_launches": nk,
+            "all_terms": all_terms, "errors": errs,
+            "slices": len(slices), "sizes": {str(n): sum(1 for s in srcs if s.nl == n)
+                                             for n in sorted({s.nl for s in srcs})}}
+
+
+def roofline(prec, terms, kernel_ms, launches, traffic=None, kernel="k_patch"):
+    """Useful matrix-core work (4 flops per term) per launch over the
+    kernel's average launch time, against the dense peak of its arithmetic;
+    the executed figure (split products and tile padding aside) beside it."""
+    per_launch_ms = kernel_ms / max(launches, 1)
+    per_launch_flops = ALG_FLOPS_PER_TERM * terms / max(launches, 1)
+    achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {"bound": "mfma", "kernel": f"{kernel}<{prec}>", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "kernel_ms": per_launch_ms, "launches": launches,
+            "frac_with_split_products": achieved * PRODUCTS[prec] / peak,
+            "per_unit": f"{ALG_FLOPS_PER_TERM:g} flops per useful one-sided term (2 real multiply-adds), "
+                        f"{terms / max(launches, 1):.4g} terms per launch on average"}
+
+
+def precision_workload(pk, torch, ps, ws, seed=0):
+    """The precision workload (K = 23.2M, 64 sources of 257^2 at 0.1-3 deg),
+    each arithmetic in one batched call: time, terms/s and the error at the
+    stored oracle pixels (four sources)."""
+    import numpy as np
+    obs = ps.observation(4, seed=seed)
+    srcs = ps.sources(4, seed=seed)
+    dobs = pk.DeviceObservation(obs)
+    terms = float(obs.K) * sum(s.nl * s.nm for s in srcs)
+    gold = golden_pixels(["config4_seed0_pixels.npy"])
+    out = {"workload": "64 antennas, 1800 x 2 s, 64 ch over 0.9-1.7 GHz, 10 s x 2 ch bins (K=23,224,320), "
+                       "64 sources at 0.1-3 deg, 257x257 at 1.5 arcsec", "K": obs.K, "sources": len(srcs)}
+    for prec in ("split_bf16", "split_fp16", "fp32"):
+        P = pk.patch_batched(dobs, srcs, prec=prec, workspace=ws)
+        torch.cuda.synchronize()
+        pk.psf_timing_read()
+        pk.psf_timing_enable(True)
+        t0 = time.perf_counter()
+        P = pk.patch_batched(dobs, srcs, prec=prec, workspace=ws, out=P)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kms, nk = pk.psf_timing_read()
+        pk.psf_timing_enable(False)
+        parts = pk.split_patches(P, srcs)
+        err = max((float(np.max(np.abs(parts[i].cpu().numpy().astype(np.float64)[ii, jj] - ref)) / abs(peak))
+                   for i, (ii, jj, ref, peak) in gold.items()), default=None)
+        out[prec] = {"s": dt, "terms_per_s": terms / dt, "psfs_per_s": len(srcs) / dt,
+                     "contraction_tflops_useful": ALG_FLOPS_PER_TERM * terms / (kms * 1e-3) / 1e12,
+                     "frac_useful": ALG_FLOPS_PER_TERM * terms / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                     "max_err_at_oracle_pixels": err}
+    out["split_bf16_over_fp32"] = out["fp32"]["s"] / out["split_bf16"]["s"]
+    del dobs
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(obs, src, n_bl_sub):
-    """The FP64 oracle (decorr + factored patch) on the first n_bl_sub baselines."""
+    """The FP64 oracle (decorr + factored patch) for one source on the first
+    n_bl_sub baselines of the workload."""
     import numpy as np
 
     import oracle as orc
@@ -250,9 +416,10 @@ def cpu_baseline(obs, src, n_bl_sub):
     terms = k1 * src.nl * src.nm
     return {"value": terms / dt, "unit": "terms/s", "cores": blas_threads or len(os.sched_getaffinity(0)),
             "kind": "oracle",
-            "sample": f"FP64 oracle decorr + factored patch over the first {B} of {obs.n_bl} baselines "
-                      f"({k1} of {obs.K} bins) x {src.nl}x{src.nm} pixels, {dt:.1f} s; host has "
-                      f"{len(os.sched_getaffinity(0))} usable cores"}
+            "sample": f"FP64 oracle decorr + factored patch of one {src.nl}x{src.nm} source over the first {B} "
+                      f"of {obs.n_bl} baselines of the headline workload ({k1} of {obs.K} bins), {dt:.1f} s; "
+                      f"host has {len(os.sched_getaffinity(0))} usable cores",
+            "cpu_model": cpu_model(), "host_cores": len(os.sched_getaffinity(0)), "blas_threads": blas_threads}
 
 
 def main():
@@ -266,11 +433,7 @@ def main():
     import paper_2009_07010_amd as pk
     import psf_synth as ps
     assert torch.cuda.is_available(), "needs a GPU"
-    obs = ps.observation(2, seed=a.seed)
-    src = ps.sources(2, seed=a.seed)[0]
-    dobs = pk.DeviceObservation(obs)
     ws = pk.Workspace()
-    terms = obs.K * src.nl * src.nm
 
     if a.copy_mib > 0:
         n = a.copy_mib * (1 << 20) // 4
@@ -282,51 +445,80 @@ def main():
         print(f"copied {a.copy_mib} MiB 3 times", flush=True)
         return
 
-    if a.profile_steps > 0:
+    if a.profile_steps > 0 and a.profile_workload == "meerkat257":
+        obs = ps.observation(2, seed=a.seed)
+        src = ps.sources(2, seed=a.seed)[0]
+        dobs = pk.DeviceObservation(obs)
         for _ in range(a.profile_steps):
             pk.patch(dobs, src, prec=a.prec, workspace=ws)
         torch.cuda.synchronize()
-        print(f"profiled {a.profile_steps} steps of {a.prec}", flush=True)
+        print(f"profiled {a.profile_steps} single PSFs of {a.prec}", flush=True)
         return
 
-    ms, kms, _ = time_prec(pk, torch, dobs, src, a.prec, a.steps, a.warmup, ws)
-    ms32, kms32, _ = time_prec(pk, torch, dobs, src, "fp32", max(3, a.steps // 4), 1, ws)
-    flops = FLOPS_PER_TERM[a.prec] * terms
-    achieved = flops / (kms * 1e-3) / 1e12
+    print("generating the headline workload", file=sys.stderr, flush=True)
+    obs5 = ps.observation(5, seed=a.seed)
+    srcs5 = ps.sources(5, seed=a.seed)
+    if a.profile_steps > 0:
+        h = headline_bda(pk, torch, ps, obs5, srcs5, a.prec, a.profile_steps, 1, ws)
+        print(f"profiled {a.profile_steps} headline steps of {a.prec}: {h['ms_per_step']:.1f} ms/step", flush=True)
+        return
+    print("timing the headline workload", file=sys.stderr, flush=True)
+    h = headline_bda(pk, torch, ps, obs5, srcs5, a.prec, a.steps, a.warmup, ws)
+    rf = roofline(a.prec, h["all_terms"], h["kernel_ms_total"], h["kernel_launches"])
     line = {
-        "metric": "PSF vis\u00b7pixel terms/s at \u22641e-5 rel err vs FP64; PSFs/s, split-BF16 vs FP32",
-        "value": terms / (ms * 1e-3),
+        "metric": "PSF vis·pixel terms/s at ≤1e-5 rel err vs FP64; PSFs/s, split-BF16 vs FP32",
+        "value": h["terms_per_s"],
         "unit": "terms/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[a.prec],
         "data": "synthetic",
-        "config": {"workload": "MeerKAT-shaped: 64 antennas (2016 baselines), 3600 x 2 s, 32 ch over "
-                               "1.3-1.5 GHz, 20 s x 4 ch bins (K=5,806,080), 1 source at 1 deg, 257x257 "
-                               "patch at 1.5 arcsec",
-                   "K": obs.K, "patch": [src.nl, src.nm], "precision": a.prec, "seed": a.seed},
-        "psfs_per_s": 1e3 / ms,
-        "fp32": {"ms_per_step": ms32, "terms_per_s": terms / (ms32 * 1e-3),
-                 "contraction_ms": kms32,
-                 "contraction_tflops": 4.0 * terms / (kms32 * 1e-3) / 1e12},
-        "roofline": {"bound": "mfma", "kernel": f"k_patch<{a.prec}>", "achieved": achieved,
-                     "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[a.prec],
-                     "traffic": measured_traffic(a.prec), "kernel_ms": kms,
-                     "per_unit": f"{FLOPS_PER_TERM[a.prec]:g} matrix-core flops per useful term, "
-                                 f"{terms} terms per launch"},
+        "config": {"workload": "baseline-dependent averaging, MeerKAT-shaped: 64 antennas (2016 baselines), "
+                               "14400 x 1 s, 64 ch over 1.3-1.5 GHz, bins floor(B_max/|b|) clamped to 1-64 "
+                               "samples x 1-8 ch, 256 sources at 0.05-3 deg with 65/129/257-pixel patches at "
+                               "1.5 arcsec; one step = one graph replay of a 16-source psf_patch_batched call",
+                   "K": obs5.K, "sources": len(srcs5), "patch_sizes": h["sizes"], "precision": a.prec,
+                   "seed": a.seed},
+        "psfs_per_s": h["psfs_per_s"],
+        "max_rel_err_vs_fp64": max(h["errors"].values()) if h["errors"] else None,
+        "errors_at_oracle_pixels": h["errors"],
+        "all_256_eager_s": h["eager_all_256_s"],
+        "roofline": rf,
     }
+    print("uniform-bin workload", file=sys.stderr, flush=True)
+    obs = ps.observation(2, seed=a.seed)
+    src = ps.sources(2, seed=a.seed)[0]
+    dobs = pk.DeviceObservation(obs)
+    terms = obs.K * src.nl * src.nm
+    ms, kms, _ = time_prec(pk, torch, dobs, src, a.prec, a.steps, a.warmup, ws)
+    ms32, kms32, _ = time_prec(pk, torch, dobs, src, "fp32", max(3, a.steps // 4), 1, ws)
+    line["meerkat257"] = {
+        "workload": "64 antennas (2016 baselines), 3600 x 2 s, 32 ch over 1.3-1.5 GHz, 20 s x 4 ch bins "
+                    "(K=5,806,080), 1 source at 1 deg, 257x257 at 1.5 arcsec, one psf_patch call per PSF",
+        "K": obs.K, "terms_per_s": terms / (ms * 1e-3), "ms_per_psf": ms, "psfs_per_s": 1e3 / ms,
+        "roofline": roofline(a.prec, float(terms), kms, 1, measured_traffic(a.prec)),
+        "fp32": {"ms_per_psf": ms32, "terms_per_s": terms / (ms32 * 1e-3),
+                 "roofline": roofline("fp32", float(terms), kms32, 1)}}
+    print("extras", file=sys.stderr, flush=True)
     line["method1"] = time_method1(pk, torch, dobs, src, a.prec, ws)
     line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)
     line["windows"], line["fullw"] = time_windows_fullw(pk, torch, ps, obs, dobs, src, a.prec, ws)
     line["method2"] = time_method2(pk, torch, ps, dobs, src, a.prec, ws)
     line["adjoint"] = time_adjoint(pk, torch, ps, dobs, a.prec, ws)
+    del dobs
+    torch.cuda.empty_cache()
+    print("precision workload", file=sys.stderr, flush=True)
+    line["precision"] = precision_workload(pk, torch, ps, ws, a.seed)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(obs, src, a.cpu_baselines)
+        print("CPU reference", file=sys.stderr, flush=True)
+        src_c = next(s for s in srcs5 if s.nl == 129)
+        cb = cpu_baseline(obs5, src_c, a.cpu_baselines)
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

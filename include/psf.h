@@ -60,13 +60,34 @@ typedef enum {
 } psf_status;
 
 /* Arithmetic of the patch contraction.  Phase arguments are always formed
- * and reduced to turns in FP64; sin/cos, D_k and accumulation are FP32. */
+ * and reduced to turns in FP64; sin/cos, D_k and accumulation are FP32.
+ * Accuracy of the split forms: an operand value v is carried as hi + lo
+ * (16 significant bits in BF16, 22 in FP16), and one term's product is off
+ * by up to 3 * 2^-16 (BF16) or 3 * 2^-22 (FP16) of |c a b|.  Over many
+ * visibilities these errors are incoherent and the patch error stays far
+ * below 1e-5 of the peak (measured 1e-7 to 6e-6 on the workloads of the
+ * tests, the largest for 120 strongly decorrelated bins); a patch of a few
+ * bins can reach the per-term bound in PSF_SPLIT_BF16 (4.6e-5 of the peak
+ * at K = 1), so every entry point that contracts takes FP32 products
+ * instead of split-BF16 ones when K < 256 (where they cost nothing
+ * measurable). */
 typedef enum {
   PSF_FP32 = 0,        /* FP32 matrix-core products, FP32 accumulation */
   PSF_SPLIT_BF16 = 1,  /* operands split hi+lo in BF16, 3 products, FP32 acc */
   PSF_SPLIT_FP16 = 2,  /* operands split hi+lo in FP16, 3 products, FP32 acc */
   PSF_PLAIN_BF16 = 3   /* single BF16 product: a negative control, not accurate */
 } psf_prec;
+
+/* Flag OR-ed into prec for psf_patch, psf_patch_batched and
+ * psf_workspace_bytes: the normalised PSF [section 4, errors taken on PSFs
+ * normalised at the source; Algorithm 2, the properly normalised PSF],
+ * P / peak with peak = 2 Re sum_k W_k D_k, the patch's value at the source
+ * itself (every phase factor is 1 there), whether or not the grid contains
+ * the source.  The peak is summed in FP64 in a fixed order from the same
+ * W_k D_k the contraction uses; the division is FP64, rounded to float.
+ * A peak of 0 (no visibility, or every weight 0) gives a patch of zeros.
+ * Other entry points reject the flag (PSF_EINVAL). */
+#define PSF_NORMALISE 0x100
 
 /* One observation: high-resolution uvw tracks, channels and the bin table
  * (all device arrays).  Bins are ordered (baseline, time bin, frequency bin):
@@ -137,13 +158,22 @@ int psf_decorr_sinc(const psf_obs* obs, double l0, double m0, float* D, void* st
 int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec,
               float* P, void* ws, size_t ws_bytes, void* stream);
 
-/* Many sources in one persistent launch: D_k and the phases are computed
- * on the fly per work item (source, k-range), so nothing of size K is kept
- * per source.  h_srcs (host) fixes sizes and offsets; d_srcs (device, same
- * n_src entries with the same nl, nm, out_off) supplies directions and
- * grids at run time, so a captured graph can be replayed with new
- * directions.  tuning_json (host, may be NULL) is a table from
- * psf_autotune.  P_all receives every patch at its out_off. */
+/* Many sources per call [section 3.3: one PSF per source direction].
+ * Sources are grouped by tile family (their patch size) and form, in groups
+ * of at most 16 whose per-bin records fit 16 GiB: each source of a group
+ * gets K records of 40 bytes (u', v' in FP64, the 16-pixel phase steps of
+ * both axes, W D), written by one decorrelation launch per source; one
+ * persistent contraction launch then runs every (source, tile, k-slice)
+ * work item of the group, and one finalise launch writes its patches.  So
+ * a call costs 3 launches per group, plus one per source, and its
+ * workspace holds one group's records: where K is large (2.65e8 bins take
+ * 10.6 GB per source) a group holds one source.  h_srcs (host) fixes sizes,
+ * offsets and the plan; d_srcs (device, same n_src entries with the same
+ * nl, nm, out_off) supplies directions and grids at run time, so a
+ * captured graph can be replayed with new directions and grids (any grid
+ * position: the plan depends on the patch sizes only).  tuning_json (host,
+ * may be NULL) is a table from psf_autotune.  P_all receives every patch at
+ * its out_off.  prec may carry PSF_NORMALISE. */
 int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                       const psf_src* d_srcs, int prec, const char* tuning_json,
                       float* P_all, void* ws, size_t ws_bytes, void* stream);
@@ -162,9 +192,11 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
  * forms five derivative patches with the forward contraction (arithmetic
  * chosen by prec) and reduces them against G.  Both accumulate in FP64 in a
  * fixed order (deterministic).
- * h_srcs (host) gives directions, grids and out_off; d_srcs is not read
- * (may be NULL).  G_all must hold every source's block: the library cannot
- * check device extents. */
+ * h_srcs (host) gives sizes and out_off, and the directions and grids
+ * when d_srcs is NULL; otherwise d_srcs (device, same entries as h_srcs)
+ * supplies directions and grids at run time, so a captured forward and
+ * backward can be replayed with new directions.  G_all must hold every
+ * source's block: the library cannot check device extents. */
 int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs,
                        const psf_src* d_srcs, const float* G_all, int prec,
                        double* grad_lm, void* ws, size_t ws_bytes, void* stream);
@@ -223,7 +255,15 @@ int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, con
  * given dL/dout, writes G[s][p] = flux[s] dL/dout[s][p] (float, the
  * cotangent psf_patch_backward takes) and grad_flux[s] = sum_p dL/dout[s][p]
  * P[s][p] (device double, FP64 products and sums in a fixed order).  flux is
- * a device float array [n_src].  n_src in 1..65535, npix in 1..2^31. */
+ * a device float array [n_src].  n_src in 1..65535, npix in 1..2^31.
+ * Accuracy: grad_flux is exact for the float P it is given, so its error is
+ * that of P.  For the fitting loss sum ||flux P - T||^2 near its optimum the
+ * terms of dL/dflux = 2 sum r P (r = flux P - T) cancel: a patch error of
+ * e (relative to the patch peak) gives an error of up to e sum |2 r P| /
+ * peak, which relative to the cancelled sum itself is measured at up to
+ * 1.6e-4 with split-BF16 patches and 8e-5 with FP32 patches on the
+ * differentiation workload (16 sources of 129^2, K = 5.8M; below 1e-5 of
+ * sum |2 r P| everywhere). */
 int psf_flux_scale(int32_t n_src, int64_t npix, const float* flux, const float* P, float* out, void* stream);
 int psf_flux_backward(int32_t n_src, int64_t npix, const float* flux, const float* P, const float* grad_out,
                       float* G, double* grad_flux, void* stream);

@@ -15,7 +15,7 @@ readings taken where the paper is silent.
 from .psf64 import (  # noqa: F401
     C_LIGHT, BinTable, bin_table, bin_centres_lambda, decorr, decorr_sinc, decorr_with_grad,
     decorr_brute, wshift, pixel_offsets, patch_factored, patch_brute, patch_pixels,
-    patch_fullw, patch_fullw_pixels, effective_psf_closed_form, peak_normalised_error, loss_value,
+    patch_fullw, patch_fullw_pixels, patch_normalised, peak_normalised_error, loss_value,
     loss_grad_analytic, loss_grad_fd, hogbom_clean, hogbom_clean_method2, OMEGA_EARTH, method2_grid, method2_dhat,
     method2_effective_psf, method2_patch,
 )

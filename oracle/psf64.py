@@ -501,19 +501,15 @@ def method2_patch(P_eff: np.ndarray, cell: float, l0: float, m0: float, dt: floa
     return out.real
 
 
-def effective_psf_closed_form(obs, src) -> np.ndarray:
-    """The effective PSF [section 2.2, inverse transform of the weighted
-    sampling function] on the patch grid about the phase centre: with D = 1
-    and no w-shift it is 2 sum_k W_k cos(2 pi (u_k l_i + v_k m_j))."""
-    uk = bin_centres_lambda(obs)
-    li = src.l_first + np.arange(src.nl) * src.dl
-    mj = src.m_first + np.arange(src.nm) * src.dm
-    out = np.zeros((src.nl, src.nm))
-    W = obs.W.astype(np.float64)
-    for i in range(src.nl):
-        ph = uk[:, 0, None] * li[i] + uk[:, 1, None] * mj[None, :]
-        out[i] = 2.0 * (W[:, None] * np.cos(TWO_PI * ph)).sum(axis=0)
-    return out
+def patch_normalised(obs, src, D: np.ndarray = None) -> np.ndarray:
+    """The normalised PSF [section 4, errors of PSFs normalised at the
+    source; Algorithm 2, the properly normalised PSF]: P / P(source), where
+    P(source) = 2 Re sum_k W_k D_k is the patch at zero offset (every phase
+    factor is 1 there), whether or not the grid holds that pixel."""
+    if D is None:
+        D = decorr(obs, src.l0, src.m0)
+    peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+    return patch_factored(obs, src, D) / peak
 
 
 def peak_normalised_error(P: np.ndarray, ref: np.ndarray):

@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsfdecorr.so")
 
 PSF_FP32, PSF_SPLIT_BF16, PSF_SPLIT_FP16, PSF_PLAIN_BF16 = 0, 1, 2, 3
+PSF_NORMALISE = 0x100
 PRECISIONS = {"fp32": PSF_FP32, "split_bf16": PSF_SPLIT_BF16, "split_fp16": PSF_SPLIT_FP16,
               "plain_bf16": PSF_PLAIN_BF16}
 PSF_OK, PSF_EINVAL, PSF_EWORKSPACE, PSF_EDEVICE, PSF_EUNSUPPORTED = 0, -1, -2, -3, -4
@@ -279,8 +280,10 @@ def decorr_sinc(dobs: DeviceObservation, l0: float, m0: float, out=None):
     return torch.view_as_complex(D)
 
 
-def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, workspace: Optional[Workspace] = None):
-    """The distorted PSF patch of one source, float32 [nl, nm]."""
+def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, workspace: Optional[Workspace] = None,
+          normalise: bool = False):
+    """The distorted PSF patch of one source, float32 [nl, nm]; with
+    ``normalise`` divided by its value at the source, 2 Re sum W D."""
     torch = _torch()
     hs = make_src(src)
     arr = (PsfSrc * 1)(hs)
@@ -291,7 +294,8 @@ def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, wor
     if D is not None:
         Dr = torch.view_as_real(D) if D.is_complex() else D
         D_ptr = Dr.data_ptr()
-    psf_patch(dobs.struct, hs, D_ptr, prec, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    code = _prec(prec) | (PSF_NORMALISE if normalise else 0)
+    psf_patch(dobs.struct, hs, D_ptr, code, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return P
 
 
@@ -337,9 +341,11 @@ def method2_patches(S, cell: float, dirs, dt_bin: float, dnu_bin: float, nu: flo
 
 
 def patch_backward(dobs: DeviceObservation, srcs: Sequence, G_all, prec="split_bf16",
-                   workspace: Optional[Workspace] = None):
+                   workspace: Optional[Workspace] = None, d_srcs=None, out=None):
     """dLoss/d(l0, m0) [n_src, 2] float64 on the device, from G_all = dLoss/dP
-    (float32, each source's [nl, nm] block concatenated in order)."""
+    (float32, each source's [nl, nm] block concatenated in order).  With
+    ``d_srcs`` (from ``device_sources``) the directions and grids are read
+    from that device array at run time, not from ``srcs``."""
     torch = _torch()
     arr = src_array(srcs)
     need = psf_workspace_bytes(dobs.struct, arr, prec)
@@ -348,19 +354,10 @@ def patch_backward(dobs: DeviceObservation, srcs: Sequence, G_all, prec="split_b
     G = G_all.to(device=dobs.device, dtype=torch.float32).contiguous()
     if G.numel() != total:
         raise ValueError(f"G_all has {G.numel()} elements, the patches {total}")
-    grad = torch.empty((len(srcs), 2), dtype=torch.float64, device=dobs.device)
-    psf_patch_backward(dobs.struct, arr, None, G.data_ptr(), prec, grad.data_ptr(), ws.data_ptr(), ws.numel(),
-                       _stream_handle())
+    grad = torch.empty((len(srcs), 2), dtype=torch.float64, device=dobs.device) if out is None else out
+    psf_patch_backward(dobs.struct, arr, None if d_srcs is None else d_srcs.data_ptr(), G.data_ptr(), prec,
+                       grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return grad
-
-
-class _Grid:
-    """A source grid with its direction replaced."""
-
-    def __init__(self, g, l0: float, m0: float):
-        self.l0, self.m0 = l0, m0
-        self.l_first, self.m_first, self.dl, self.dm = g.l_first, g.m_first, g.dl, g.dm
-        self.nl, self.nm = g.nl, g.nm
 
 
 def _psf_patch_fn():
@@ -369,31 +366,36 @@ def _psf_patch_fn():
     class PsfPatchFn(torch.autograd.Function):
         """flux_s * P_s(l0_s, m0_s) for every source, [n_src, nl, nm] float32.
 
-        ``lm0`` float64 [n_src, 2] (any device; read on the host), ``flux``
+        ``lm0`` float64 [n_src, 2] on the observation's device, ``flux``
         [n_src]; ``grids`` gives each source's fixed pixel grid (l_first,
-        m_first, dl, dm, nl, nm, all patches the same size).  The backward
-        returns dLoss/d(lm0) from the library's adjoint (``psf_patch_backward``)
-        and dLoss/d(flux) = sum(grad_out * P_s) (``psf_flux_backward``).
+        m_first, dl, dm, nl, nm, all patches the same size).  ``lm0`` is
+        written into the device source array ``d_srcs`` (from
+        ``device_sources(grids)``; made here when not given, which copies
+        from the host and so cannot be captured), then one batched forward
+        call (``psf_patch_batched``) and one flux scaling run; the backward
+        is one ``psf_flux_backward`` and one ``psf_patch_backward`` reading
+        the same device array.  Nothing is read back to the host, so a
+        forward and backward with a given ``d_srcs`` and ``workspace`` can be
+        captured into a graph and replayed for new ``lm0``.
         """
 
         @staticmethod
-        def forward(ctx, lm0, flux, dobs, grids, prec="split_bf16", workspace=None):
+        def forward(ctx, lm0, flux, dobs, grids, prec="split_bf16", workspace=None, d_srcs=None):
             shapes = {(int(g.nl), int(g.nm)) for g in grids}
-            if len(shapes) != 1 or lm0.shape != (len(grids), 2) or flux.shape != (len(grids),):
+            if len(shapes) != 1 or tuple(lm0.shape) != (len(grids), 2) or tuple(flux.shape) != (len(grids),):
                 raise ValueError("need lm0 [n_src, 2], flux [n_src] and equal patch sizes")
             nl, nm = shapes.pop()
-            lm = lm0.detach().to("cpu", torch.float64)
-            srcs = [_Grid(g, float(lm[s, 0]), float(lm[s, 1])) for s, g in enumerate(grids)]
+            n = len(grids)
+            if d_srcs is None:
+                d_srcs = device_sources(grids, dobs.device)[1]
+            set_directions(d_srcs, lm0.detach().to(dtype=torch.float64))
             ws = workspace or Workspace(dobs.device)
-            P = torch.empty((len(srcs), nl, nm), dtype=torch.float32, device=dobs.device)
-            for s, src in enumerate(srcs):
-                patch(dobs, src, prec=prec, out=P[s], workspace=ws)
+            P = patch_batched(dobs, grids, prec=prec, workspace=ws, d_srcs=d_srcs).view(n, nl, nm)
             f = flux.detach().to(device=dobs.device, dtype=torch.float32).contiguous()
             out = torch.empty_like(P)
-            _check(lib().psf_flux_scale(len(srcs), nl * nm, f.data_ptr(), P.data_ptr(), out.data_ptr(),
-                                        _stream_handle()))
+            _check(lib().psf_flux_scale(n, nl * nm, f.data_ptr(), P.data_ptr(), out.data_ptr(), _stream_handle()))
             ctx.save_for_backward(P, f)
-            ctx.srcs, ctx.dobs, ctx.prec, ctx.ws = srcs, dobs, prec, ws
+            ctx.grids, ctx.dobs, ctx.prec, ctx.ws, ctx.d_srcs = grids, dobs, prec, ws, d_srcs
             ctx.lm_device, ctx.flux_device, ctx.flux_dtype = lm0.device, flux.device, flux.dtype
             return out
 
@@ -407,8 +409,8 @@ def _psf_patch_fn():
             _check(lib().psf_flux_backward(n, nl * nm, f.data_ptr(), P.data_ptr(), go.data_ptr(), G.data_ptr(),
                                            gflux.data_ptr(), _stream_handle()))
             grad_flux = gflux.to(device=ctx.flux_device, dtype=ctx.flux_dtype)
-            grad_lm = patch_backward(ctx.dobs, ctx.srcs, G, ctx.prec, ctx.ws).to(ctx.lm_device)
-            return grad_lm, grad_flux, None, None, None, None
+            grad_lm = patch_backward(ctx.dobs, ctx.grids, G, ctx.prec, ctx.ws, d_srcs=ctx.d_srcs).to(ctx.lm_device)
+            return grad_lm, grad_flux, None, None, None, None, None
 
     return PsfPatchFn
 
@@ -438,7 +440,8 @@ def device_sources(srcs: Sequence, device="cuda"):
 
 def set_directions(d_srcs, lm0) -> None:
     """Overwrite (l0, m0) of every source in a device source array with the
-    rows of ``lm0`` (float64 [n_src, 2], same device); grids stay."""
+    rows of ``lm0`` (float64 [n_src, 2], same device); grids stay.  A
+    device-to-device copy on the current stream (capturable)."""
     torch = _torch()
     n = lm0.shape[0]
     rec = ctypes.sizeof(PsfSrc) // 8
@@ -447,17 +450,19 @@ def set_directions(d_srcs, lm0) -> None:
 
 
 def patch_batched(dobs: DeviceObservation, srcs: Sequence, prec="split_bf16", tuning: Optional[str] = None,
-                  out=None, workspace: Optional[Workspace] = None, d_srcs=None):
+                  out=None, workspace: Optional[Workspace] = None, d_srcs=None, normalise: bool = False):
     """Every source's patch in one call, concatenated float32 [sum nl*nm] in
     source order (``split_patches`` cuts it).  ``d_srcs`` (from
-    ``device_sources``) may be passed to reuse a device source array."""
+    ``device_sources``) may be passed to reuse a device source array;
+    ``normalise`` divides each patch by its value at its source."""
     torch = _torch()
     h, d = device_sources(srcs, dobs.device) if d_srcs is None else (src_array(srcs), d_srcs)
     need = psf_workspace_bytes(dobs.struct, h, prec)
     ws = (workspace or Workspace(dobs.device)).get(need)
     total = sum(int(s.nl) * int(s.nm) for s in srcs)
     P = torch.empty(total, dtype=torch.float32, device=dobs.device) if out is None else out
-    psf_patch_batched(dobs.struct, h, d.data_ptr(), prec, None if tuning is None else tuning.encode(),
+    code = _prec(prec) | (PSF_NORMALISE if normalise else 0)
+    psf_patch_batched(dobs.struct, h, d.data_ptr(), code, None if tuning is None else tuning.encode(),
                       P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
     return P
 

@@ -240,15 +240,16 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
 }
 
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
-                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream) {
+                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream,
+                         const double* dir) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
   if (coef_out != nullptr && D_in == nullptr)
     hipLaunchKernelGGL(k_decorr<true>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0,
-                       dl, dm, nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
+                       dl, dm, dir, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
   else
     hipLaunchKernelGGL(k_decorr<false>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0,
-                       dl, dm, nullptr, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, nullptr);
+                       dl, dm, dir, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, nullptr);
   return hipGetLastError();
 }
 

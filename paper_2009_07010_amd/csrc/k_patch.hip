@@ -42,6 +42,28 @@
 // Split forms: every operand value v is stored as hi = round16(v) and
 // lo = round16(v - hi); the product uses hi*hi + hi*lo + lo*hi (three MFMAs)
 // with FP32 accumulation.
+//
+// Symmetric form.  With N = 2h + 1 rows, x_i = delta + (i - h) dl where
+// delta = (l_first + h dl) - l0 is the offset of the grid's centre row from
+// the source (0 for a centred grid), so a_ki = e_k a_k(s_i) with
+// e_k = exp(2 pi i u'_k delta) and s_i = (i - h) dl symmetric about 0;
+// a_k(-s) = conj(a_k(s)), so with C = Re a and S = Im a (even and odd in s)
+// and d_kj = c_k e_k b_kj,
+//   P(+-s, y_j) = 2 sum_k [C_k(s) Re d_kj -+ S_k(s) Im d_kj],   s >= 0.
+// The contraction then runs over an inner dimension of K real values
+// (instead of 2K) into an output of h + 1 "C" rows (x = 0 .. h, against
+// Re d) and h "S" rows (x = 1 .. h, against Im d): half the multiply-adds
+// of the general form, for the same (2h + 1) x N output.  C rows sit at
+// output rows x + 15 of the first CB blocks, S rows at 16 CB + x - 1 of the
+// blocks after (h a multiple of 16, CB = h/16 + 1), so a generating thread
+// with row class rc walks one phase sequence x = rc - 15 + 16 n and writes
+// its cosine to C row block n and its sine to S row block CB + n - 1.
+// Rows 0..14 (x < 0) are never read.  B columns carry c_k b_kj, its real
+// part in one LDS plane and its imaginary part in another; a contraction
+// wave's rows lie in one group and read the matching plane.  K-f combines
+// the C and S rows of |x| into the rows +x and -x.
+#include <type_traits>
+
 #include "psf_device.hpp"
 #include "psf_kernels.hpp"
 
@@ -72,6 +94,9 @@ struct TileArgs {
   const BinRec* rec;
   const float2* c;
   double l_first, dl, l0, m_first, dm, m0;
+  // symmetric form: offset of the grid's centre row from the source,
+  // (l_first + h dl) - l0 (0 for a grid centred on the source)
+  double delta_l;
   int flush_chunks;
 };
 
@@ -118,8 +143,19 @@ __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int g
   }
 }
 
+// Leading C blocks (rows of the symmetric form's C group) of each tile
+// type of the symmetric families: 257 rows (tiles of 9 C blocks and 8 S
+// blocks), 129 (one tile, 5 + 4), 65 (one tile, 3 + 2); -1 otherwise.
+__host__ __device__ constexpr int sym_cb(int TBI, int TBJ) {
+  return (TBJ == 17 && TBI == 9) ? 9
+         : (TBJ == 17 && TBI == 8) ? 0
+         : (TBI == 9 && TBJ == 9)  ? 5
+         : (TBI == 5 && TBJ == 5)  ? 3
+                                   : -1;
+}
+
 // LDS geometry of one tile type: two operand buffers.
-template <int PREC, int TBI, int TBJ>
+template <int PREC, int TBI, int TBJ, bool SYM = false>
 struct TileGeom {
   static constexpr int TI = 16 * TBI, TJ = 16 * TBJ;
   static constexpr int RA = TI / 8, RB = TJ / 8;  // rows per generator thread (stride 8)
@@ -128,7 +164,13 @@ struct TileGeom {
   static constexpr int GA = TI * kRowBytes, GB = TJ * kRowBytes;  // one group / plane
   static constexpr int APL = (F32 ? 2 : 1) * GA, BPL = (F32 ? 2 : 1) * GB;
   static constexpr int NPL = TWO ? 2 : 1;
-  static constexpr int BUF = NPL * (APL + BPL);
+  // symmetric form: C blocks of the tile, and B planes (Re d and Im d when
+  // the tile holds both groups, else the one its rows read)
+  static constexpr int CB = SYM ? sym_cb(TBI, TBJ) : TBI;
+  static constexpr int NBP = SYM && CB > 0 && CB < TBI ? 2 : 1;
+  static constexpr int BUF = NPL * (APL + NBP * BPL);
+  // byte offset of B's part (0 hi, 1 lo) of plane pl within a buffer
+  static constexpr int boff(int part, int pl) { return NPL * APL + (pl * NPL + part) * BPL; }
   // Chunk buffers.  2: the chunk being contracted and the chunk being
   // generated.  3: also the next chunk, complete one barrier early, so that
   // its first operand fragments can be read ahead of the barrier (measured
@@ -136,6 +178,7 @@ struct TileGeom {
   static constexpr int NBUF = 2;
   static constexpr int LDS = NBUF * BUF;
   static_assert(LDS <= 160 * 1024, "LDS of a workgroup exceeds 160 KiB");
+  static_assert(!SYM || CB >= 0, "no symmetric form for this tile type");
 };
 
 // Sub-tile of one contraction wave: m x n blocks at block (i0, j0) of the
@@ -147,7 +190,19 @@ struct WaveShape {
 };
 __host__ __device__ constexpr uint64_t full_mask(int m, int n) { return m * n == 64 ? ~0ULL : (1ULL << (m * n)) - 1; }
 
-__host__ __device__ constexpr WaveShape wave_shape(int TBI, int TBJ, int w) {
+__host__ __device__ constexpr WaveShape wave_shape(int TBI, int TBJ, int w, bool sym = false) {
+  // Symmetric 9 x 9 tile: waves 0-3 take the 5 C block rows, waves 4-7 the
+  // 4 S block rows (a wave's rows must lie in one group), columns split so
+  // that the busiest SIMD has 22 blocks (5 a + 4 b per SIMD: 21, 22, 19, 19).
+  if (sym && TBI == 9 && TBJ == 9) {
+    const int a[4] = {1, 2, 3, 3};
+    const int b[4] = {4, 3, 1, 1};
+    const int s = w & 3;
+    int j0 = 0;
+    for (int q = 0; q < s; ++q) j0 += w < 4 ? a[q] : b[q];
+    const int m = w < 4 ? 5 : 4, n = w < 4 ? a[s] : b[s];
+    return {m, n, w < 4 ? 0 : 5, j0, full_mask(m, n)};
+  }
   if (TBI == 9 && TBJ == 17) {
     // 153 blocks, at most 20 per wave: four 5x4 sub-tiles over rows 0-4 and
     // columns 0-15, three 4x5 over rows 5-8 and columns 0-14, and the rest
@@ -197,12 +252,14 @@ __device__ __forceinline__ void store_data_guard() {
 // True if the eight contraction-wave sub-tiles cover every block of the tile
 // exactly once and no sub-tile holds more than 30 blocks (120 accumulator
 // registers).
-template <int TBI, int TBJ>
+template <int TBI, int TBJ, bool SYM = false>
 constexpr bool wave_shapes_ok() {
   int cover[TBI * TBJ] = {};
   for (int w = 0; w < 8; ++w) {
-    const WaveShape s = wave_shape(TBI, TBJ, w);
+    const WaveShape s = wave_shape(TBI, TBJ, w, SYM);
     if (s.m * s.n > 64 || s.i0 + s.m > TBI || s.j0 + s.n > TBJ) return false;
+    // symmetric form: a wave's rows lie in one group (C or S)
+    if (SYM && !(s.i0 + s.m <= sym_cb(TBI, TBJ) || s.i0 >= sym_cb(TBI, TBJ))) return false;
     int nb = 0;
     for (int r = 0; r < s.m; ++r)
       for (int c = 0; c < s.n; ++c)
@@ -335,23 +392,205 @@ struct Gen {
   }
 };
 
+// Store two real operand values of visibilities 2 gv and 2 gv + 1 (of the
+// 32 of a symmetric-form chunk) at `row` of a plane.  16-bit: k index
+// within the row = visibility, one 32-bit store of the packed pair (hi),
+// one of lo.  FP32: two groups of 16 visibilities (group stride gstride),
+// within a group visibility 4 c + e at float e of 16-byte chunk c (lane
+// group c of the 16x16x4 instruction takes chunk c, k-step e float e), so
+// the pair is one 8-byte store.
+template <int PREC>
+__device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstride, int row, int gv, float v0,
+                                           float v1) {
+  typedef __attribute__((address_space(3))) f32x2_t lds_f32x2;
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
+  if constexpr (PREC == kFP32) {
+    lds_t* p = hi_plane + (gv >> 3) * gstride + row * kRowBytes + swz(row, (gv & 7) >> 1) + (gv & 1) * 8;
+    *reinterpret_cast<lds_f32x2*>(p) = f32x2_t{v0, v1};
+  } else {
+    lds_t* p = hi_plane + row * kRowBytes + swz(row, gv >> 2) + (gv & 3) * 4;
+    uint32_t hi, lo = 0;
+    if constexpr (PREC == kSplitFP16) {
+      hi = pack_f16x2(v0, v1);
+      lo = pack_f16x2(v0 - f16_lo_to_f32(hi), v1 - f16_hi_to_f32(hi));
+    } else {
+      hi = pack_bf16x2(v0, v1);
+      if constexpr (PREC == kSplitBF16) lo = pack_bf16x2(v0 - bf16_lo_to_f32(hi), v1 - bf16_hi_to_f32(hi));
+    }
+    *reinterpret_cast<lds_u32*>(p) = hi;
+    if constexpr (PREC != kPlainBF16) *reinterpret_cast<lds_u32*>(p + lo_off) = lo;
+  }
+}
+
+// Phase-factor generation of the symmetric form (see the file comment).
+// Thread (gv, rc) owns visibilities 2 gv and 2 gv + 1 of each 32-visibility
+// chunk and row (column) class rc.  A (waves 0-3): unit n of its sequence
+// is x = (rc - 15 + 16 n) dl; it writes Re a to C row 16 n + rc (n < CB)
+// and Im a to S row 16 (CB + n - 1) + rc (n >= 1).  B (waves 4-7): unit q
+// is column 16 q + rc, y its offset from m0; it writes Re and/or Im of
+// d = c b to the tile's B plane(s).  Seeds are FP64-reduced and evaluated
+// once (hardware sine and cosine), the 16-row steps come with the bin's
+// record; along the units the split forms use the real three-term
+// recurrence (one fused multiply-add per written value; both parts when
+// both are written), the FP32 form the complex product.  Past the end of
+// the slice the last bin is read and its coefficient (carried by B) is 0.
+template <int PREC, int TBI, int TBJ, bool IS_A>
+struct GenSym {
+  using G = TileGeom<PREC, TBI, TBJ, true>;
+  static constexpr int CB = G::CB;
+  static constexpr bool HC = CB > 0, HS = CB < TBI;
+  static constexpr int N0 = IS_A && !HC ? 1 : 0;
+  static constexpr int NA = (HC ? CB - 1 : 0) > (HS ? TBI - CB : 0) ? (HC ? CB - 1 : 0) : (HS ? TBI - CB : 0);
+  static constexpr int R = IS_A ? NA - N0 + 1 : TBJ;  // generator units per chunk
+  // which parts of the factor are written: both, or only the imaginary one
+  static constexpr bool BOTH = IS_A ? (HC && HS) : G::NBP == 2;
+  static constexpr bool ONLY_IM = !BOTH && (IS_A ? !HC : CB == 0);
+  static constexpr int GSTRIDE = IS_A ? G::GA : G::GB;
+  static constexpr int LO = IS_A ? G::APL : G::BPL;
+  static constexpr int P = 1;  // chunks of records held ahead
+
+  int gv, rc;
+  double pos0;
+  const BinRec* recs;
+  const float2* cptr;
+  int64_t kb, ke;
+  double delta;  // B: the grid centre's offset from the source along l
+  double rf[P][2];
+  double ru[P][2];  // B: u' (for the offset factor)
+  cf32 rst[P][2];
+  cf32 rcc[P][2];
+  bool rok[P][2];
+  cf32 z[2], zp[2];
+  float tc[2];
+  lds_t* plane;
+
+  __device__ __forceinline__ GenSym(const TileArgs& a, int wave, int bi0, int bj0, int64_t kb_, int64_t ke_) {
+    (void)bi0;
+    const int lane = threadIdx.x & 63;
+    gv = lane & 15;
+    rc = 4 * (wave & 3) + (lane >> 4);
+    pos0 = IS_A ? static_cast<double>(rc - 15 + 16 * N0) * a.dl : (a.m_first + (16 * bj0 + rc) * a.dm) - a.m0;
+    delta = a.delta_l;
+    recs = a.rec;
+    cptr = a.c;
+    kb = kb_;
+    ke = ke_;
+  }
+  __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok) const {
+    const int64_t kg = kb + n * kPatchChunkSym + 2 * gv + e;
+    ok = kg < ke;
+    const int64_t kc = ok ? kg : ke - 1;
+    const BinRec* r = recs + kc;
+    f = IS_A ? r->up : r->vp;
+    const float2 s = IS_A ? r->step_a : r->step_b;
+    st = {s.x, s.y};
+    if (!IS_A) {
+      u = r->up;
+      const float2 c = cptr[kc];
+      cc = {c.x, c.y};
+    }
+  }
+  __device__ __forceinline__ void prime() {
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) fetch(j, e, rf[j][e], ru[j][e], rst[j][e], rcc[j][e], rok[j][e]);
+  }
+  __device__ __forceinline__ void begin(lds_t* smem, int buf) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      z[e] = expi_turns_hw(rf[0][e] * pos0);
+      const cf32 zs = rst[0][e];
+      if (!IS_A) {
+        cf32 cc = rok[0][e] ? rcc[0][e] : cf32{0.f, 0.f};
+        // a grid not centred on the source: the row-independent factor
+        // exp(2 pi i u' delta) joins the coefficient (FP64-reduced, used once)
+        if (delta != 0.0) cc = cmul(cc, expi_turns_hw(ru[0][e] * delta));
+        z[e] = cmul(cc, z[e]);
+      }
+      if constexpr (PREC == kFP32) {
+        zp[e] = zs;
+      } else {
+        zp[e] = cmul(z[e], conj(zs));  // the unit before the seed
+        tc[e] = 2.0f * zs.re;
+      }
+    }
+    plane = smem + buf * G::BUF + (IS_A ? 0 : G::boff(0, 0));
+  }
+  __device__ __forceinline__ void step() {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if constexpr (PREC == kFP32) {
+        z[e] = cmul(z[e], zp[e]);
+      } else {
+        cf32 zn = z[e];
+        if (BOTH || !ONLY_IM) zn.re = __builtin_fmaf(tc[e], z[e].re, -zp[e].re);
+        if (BOTH || ONLY_IM) zn.im = __builtin_fmaf(tc[e], z[e].im, -zp[e].im);
+        zp[e] = z[e];
+        z[e] = zn;
+      }
+    }
+  }
+  // Units [q0, q1) of the current chunk.
+  __device__ __forceinline__ void rows(int q0, int q1) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q < q0 || q >= q1) continue;
+      if constexpr (IS_A) {
+        const int n = N0 + q;
+        if (HC && n < CB) store_pair<PREC>(plane, LO, GSTRIDE, 16 * n + rc, gv, z[0].re, z[1].re);
+        if (HS && n >= 1 && CB + n - 1 < TBI)
+          store_pair<PREC>(plane, LO, GSTRIDE, 16 * (CB + n - 1) + rc, gv, z[0].im, z[1].im);
+      } else {
+        if constexpr (BOTH) {
+          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
+          store_pair<PREC>(plane + G::NPL * G::BPL, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
+        } else if constexpr (ONLY_IM) {
+          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
+        } else {
+          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
+        }
+      }
+      if (q + 1 < R) step();
+    }
+  }
+  __device__ __forceinline__ void advance(int64_t n) {
+#pragma unroll
+    for (int j = 0; j + 1 < P; ++j)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        rf[j][e] = rf[j + 1][e];
+        ru[j][e] = ru[j + 1][e];
+        rst[j][e] = rst[j + 1][e];
+        rcc[j][e] = rcc[j + 1][e];
+        rok[j][e] = rok[j + 1][e];
+      }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) fetch(n, e, rf[P - 1][e], ru[P - 1][e], rst[P - 1][e], rcc[P - 1][e], rok[P - 1][e]);
+  }
+};
+
 // One wave on one work item: the contraction of its sub-tile (K-c) for
 // chunk n, interleaved with the generation of its rows of chunk n + 1 into
 // the other LDS buffer, then one barrier.  Its second-level accumulators
 // are its blocks of the workgroup's partial slab in global memory, laid out
 // [block][lane][4] in accumulator lane order (block = tile row block * TBJ +
 // tile column block).
-template <int PREC, int TBI, int TBJ, int W>
+template <int PREC, int TBI, int TBJ, int W, bool SYM = false>
 __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi0, int bj0, int64_t kb, int64_t ke,
                                           float* __restrict__ slab) {
-  static_assert(wave_shapes_ok<TBI, TBJ>(), "contraction waves must cover the tile once");
-  using G = TileGeom<PREC, TBI, TBJ>;
-  constexpr WaveShape S = wave_shape(TBI, TBJ, W);
+  static_assert(wave_shapes_ok<TBI, TBJ, SYM>(), "contraction waves must cover the tile once");
+  using G = TileGeom<PREC, TBI, TBJ, SYM>;
+  constexpr WaveShape S = wave_shape(TBI, TBJ, W, SYM);
   constexpr int M = S.m, N = S.n, WI0 = S.i0, WJ0 = S.j0;
   constexpr auto on = [](int r, int c) { return ((S.mask >> (r * N + c)) & 1) != 0; };
   constexpr bool IS_A = W < 4;
-  using Gn = Gen<PREC, TBI, TBJ, IS_A>;
+  using Gn = std::conditional_t<SYM, GenSym<PREC, TBI, TBJ, IS_A>, Gen<PREC, TBI, TBJ, IS_A>>;
   constexpr int R = Gn::R;
+  // visibilities per chunk, and the B plane this wave's rows read (the
+  // symmetric form's S rows read Im d when the tile holds both groups)
+  constexpr int CH = SYM ? kPatchChunkSym : kChunk;
+  constexpr int BP = G::NBP == 2 && WI0 >= G::CB ? 1 : 0;
   // generation rows spread over the contraction steps of a chunk
   constexpr int NSTEP = G::F32 ? 2 * N : N + M;
   typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
@@ -373,7 +612,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
     store_data_guard();
   };
 
-  const int64_t nch = ke > kb ? (ke - kb + kChunk - 1) / kChunk : 0;
+  const int64_t nch = ke > kb ? (ke - kb + CH - 1) / CH : 0;
   Gn gen(a, W, bi0, bj0, kb, ke);
   // With NBUF chunk buffers, chunks 0 .. NBUF - 2 are generated before the
   // loop; in the loop, chunk n is contracted from buffer n mod NBUF while
@@ -402,8 +641,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
     return *reinterpret_cast<const lds_bf16x8*>(Ah + plane * G::APL + (16 * (WI0 + r) + lr) * kRowBytes + rd);
   };
   auto ldB = [&](const lds_t* Ah, int plane, int c) {
-    return *reinterpret_cast<const lds_bf16x8*>(Ah + G::NPL * G::APL + plane * G::BPL + (16 * (WJ0 + c) + lr) * kRowBytes +
-                                                rd);
+    return *reinterpret_cast<const lds_bf16x8*>(Ah + G::boff(plane, BP) + (16 * (WJ0 + c) + lr) * kRowBytes + rd);
   };
   auto ldA32 = [&](const lds_t* Ah, int g, int r) {
     return *reinterpret_cast<const lds_f32x4*>(Ah + g * G::GA + (16 * (WI0 + r) + lr) * kRowBytes + rd);
@@ -432,7 +670,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
       const int nxt = cur + 1 == NB ? 0 : cur + 1;
       const int gen_buf = NB == 2 ? nxt : (nxt + 1 == NB ? 0 : nxt + 1);
       const lds_t* Ah = buf_at(cur);
-      const lds_t* Bh = Ah + G::NPL * G::APL;
+      const lds_t* Bh = Ah + G::boff(0, BP);
       if (NB == 2) prefetch(Ah);
       // Chunk n + NBUF - 1 (past the end near the last chunk: zero weights,
       // written into an idle buffer and never read).
@@ -556,11 +794,11 @@ __host__ __device__ inline int64_t tile_first_elem(const TP& t, int ti, int tj) 
          cb * t.ns[r][1] * slab_elems(t, r, 1);
 }
 
-int tile_max_simd_blocks(int tbi, int tbj) {
+int tile_max_simd_blocks(int tbi, int tbj, bool sym) {
   int mx = 0;
   for (int q = 0; q < 4; ++q) {
     int nb = 0;
-    for (int w = q; w < 8; w += 4) nb += __builtin_popcountll(wave_shape(tbi, tbj, w).mask);
+    for (int w = q; w < 8; w += 4) nb += __builtin_popcountll(wave_shape(tbi, tbj, w, sym).mask);
     mx = nb > mx ? nb : mx;
   }
   return mx;
@@ -644,6 +882,7 @@ __device__ __forceinline__ Item decode_item(const BatchArgs& a, karg_plan* plans
     it.ta.dl = p.dl;
     it.ta.dm = p.dm;
   }
+  it.ta.delta_l = (it.ta.l_first + ((p.nl - 1) / 2) * it.ta.dl) - it.ta.l0;
   return it;
 }
 
@@ -652,27 +891,28 @@ __device__ __forceinline__ Item decode_item(const BatchArgs& a, karg_plan* plans
 // barrier of an item orders its LDS reads before the next item's first LDS
 // writes.  Each role has its own loop so that what the compiler keeps live
 // across items is only that role's.
-template <int PREC, int I0, int I1, int J0, int J1, int ROLE>
+template <int PREC, int I0, int I1, int J0, int J1, int ROLE, bool SYM>
 __device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, lds_t* smem) {
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const Item it = decode_item(a, plans, item);
     switch (it.type) {
-      case 0: wave_item<PREC, I0, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      case 1: wave_item<PREC, I0, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      case 2: wave_item<PREC, I1, J0, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
-      default: wave_item<PREC, I1, J1, ROLE>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 0: wave_item<PREC, I0, J0, ROLE, SYM>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 1: wave_item<PREC, I0, J1, ROLE, SYM>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      case 2: wave_item<PREC, I1, J0, ROLE, SYM>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
+      default: wave_item<PREC, I1, J1, ROLE, SYM>(it.ta, smem, it.bi0, it.bj0, it.kb, it.ke, it.slab); break;
     }
   }
 }
 
 // The contraction kernel: a persistent loop over the work items of the
 // launch's sources.  Template arguments are the two tile heights and the two
-// tile widths (in blocks) of its tile family.
-template <int PREC, int I0, int I1, int J0, int J1>
+// tile widths (in blocks) of its tile family, and the form (general or
+// symmetric) of every source of the launch.
+template <int PREC, int I0, int I1, int J0, int J1, bool SYM>
 __global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
 void k_patch(BatchArgs a) {
-  constexpr int L00 = TileGeom<PREC, I0, J0>::LDS, L01 = TileGeom<PREC, I0, J1>::LDS;
-  constexpr int L10 = TileGeom<PREC, I1, J0>::LDS, L11 = TileGeom<PREC, I1, J1>::LDS;
+  constexpr int L00 = TileGeom<PREC, I0, J0, SYM>::LDS, L01 = TileGeom<PREC, I0, J1, SYM>::LDS;
+  constexpr int L10 = TileGeom<PREC, I1, J0, SYM>::LDS, L11 = TileGeom<PREC, I1, J1, SYM>::LDS;
   constexpr int LA = L00 > L01 ? L00 : L01, LB = L10 > L11 ? L10 : L11;
   __shared__ __attribute__((aligned(16))) uint8_t smem_raw[LA > LB ? LA : LB];
   lds_t* smem = (lds_t*)smem_raw;
@@ -683,27 +923,21 @@ void k_patch(BatchArgs a) {
   karg_plan* plans = (karg_plan*)((karg_byte*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(BatchArgs, src));
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   switch (wave) {
-    case 0: role_loop<PREC, I0, I1, J0, J1, 0>(a, plans, smem); break;
-    case 1: role_loop<PREC, I0, I1, J0, J1, 1>(a, plans, smem); break;
-    case 2: role_loop<PREC, I0, I1, J0, J1, 2>(a, plans, smem); break;
-    case 3: role_loop<PREC, I0, I1, J0, J1, 3>(a, plans, smem); break;
-    case 4: role_loop<PREC, I0, I1, J0, J1, 4>(a, plans, smem); break;
-    case 5: role_loop<PREC, I0, I1, J0, J1, 5>(a, plans, smem); break;
-    case 6: role_loop<PREC, I0, I1, J0, J1, 6>(a, plans, smem); break;
-    default: role_loop<PREC, I0, I1, J0, J1, 7>(a, plans, smem); break;
+    case 0: role_loop<PREC, I0, I1, J0, J1, 0, SYM>(a, plans, smem); break;
+    case 1: role_loop<PREC, I0, I1, J0, J1, 1, SYM>(a, plans, smem); break;
+    case 2: role_loop<PREC, I0, I1, J0, J1, 2, SYM>(a, plans, smem); break;
+    case 3: role_loop<PREC, I0, I1, J0, J1, 3, SYM>(a, plans, smem); break;
+    case 4: role_loop<PREC, I0, I1, J0, J1, 4, SYM>(a, plans, smem); break;
+    case 5: role_loop<PREC, I0, I1, J0, J1, 5, SYM>(a, plans, smem); break;
+    case 6: role_loop<PREC, I0, I1, J0, J1, 6, SYM>(a, plans, smem); break;
+    default: role_loop<PREC, I0, I1, J0, J1, 7, SYM>(a, plans, smem); break;
   }
 }
 
-// K-f: P = 2 * sum over the k-slices of the pixel's tile, in slice order.
-// Grid row y is source y of the launch.
-__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
-  (void)a;
-  typedef const __attribute__((address_space(4))) uint8_t karg_byte;
-  karg_plan& p = ((karg_plan*)((karg_byte*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(BatchArgs, src)))[blockIdx.y];
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= static_cast<int64_t>(p.nl) * p.nm) return;
+// Sum over the k-slices of one element (row i, column j of the
+// contraction's output) of a source's partial slabs, in slice order.
+__device__ __forceinline__ float slab_sum(karg_plan& p, int i, int j) {
   const auto& t = p.tp;
-  const int i = static_cast<int>(idx / p.nm), j = static_cast<int>(idx - static_cast<int64_t>(i) * p.nm);
   const int span_i = t.ti_a * 16 * t.tbi[0], span_j = t.tj_a * 16 * t.tbj[0];
   const int r = i < span_i ? 0 : 1, c = j < span_j ? 0 : 1;
   const int hi = 16 * t.tbi[r], wj = 16 * t.tbj[c];  // tile height and width in pixels
@@ -730,7 +964,65 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
     for (int u = 0; u < 16; ++u) sum += v[u];
   }
   for (; n < nsl; ++n) sum += q[n * slab];
-  p.P[idx] = 2.0f * sum;
+  return sum;
+}
+
+// a6: P / peak, FP64 division; 0 where the peak is 0 (no visibility or
+// every weight 0: the normalised PSF is undefined).
+__device__ __forceinline__ float normalised(float v, double peak) {
+  return peak != 0.0 ? static_cast<float>(static_cast<double>(v) / peak) : 0.0f;
+}
+
+// K-f: P = 2 * sum over the k-slices of the pixel's tile, in slice order.
+// Grid row y is source y of the launch.
+__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
+  (void)a;
+  typedef const __attribute__((address_space(4))) uint8_t karg_byte;
+  karg_plan& p = ((karg_plan*)((karg_byte*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(BatchArgs, src)))[blockIdx.y];
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(p.nl) * p.nm) return;
+  const int i = static_cast<int>(idx / p.nm), j = static_cast<int>(idx - static_cast<int64_t>(i) * p.nm);
+  if (p.sym) {
+    // symmetric form: row i has offset s = i - h from the grid's centre row;
+    // C row |s| + 15 and S row 16 CB + |s| - 1 of the contraction give
+    // P(+-|s|) = 2 (C -+ S)
+    const int h = (p.nl - 1) / 2, cb = h / 16 + 1;
+    const int s = i - h, as = s < 0 ? -s : s;
+    const float c = slab_sum(p, as + 15, j);
+    const float sn = as > 0 ? slab_sum(p, 16 * cb + as - 1, j) : 0.f;
+    const float v = 2.0f * (s >= 0 ? c - sn : c + sn);
+    p.P[idx] = p.peak == nullptr ? v : normalised(v, *p.peak);
+    return;
+  }
+  const float v = 2.0f * slab_sum(p, i, j);
+  p.P[idx] = p.peak == nullptr ? v : normalised(v, *p.peak);
+}
+
+// a6: one block per range of K; FP64 sum of Re c in a fixed order
+__global__ __launch_bounds__(256) void k_peak_partial(const float2* __restrict__ c, int64_t K,
+                                                      double* __restrict__ part) {
+  const int64_t span = (K + kPeakBlocks - 1) / kPeakBlocks;
+  const int64_t k0 = blockIdx.x * span, k1 = min(K, k0 + span);
+  double acc = 0.0;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) acc += static_cast<double>(c[k].x);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double w[4];
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((w[0] + w[1]) + w[2]) + w[3];
+}
+
+__global__ __launch_bounds__(64) void k_peak_final(const double* __restrict__ part, double* __restrict__ peak) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < kPeakBlocks; b += 64) acc += part[b];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (threadIdx.x == 0) *peak = 2.0 * acc;
+}
+
+hipError_t launch_peak(const float2* c, int64_t K, double* scratch, double* peak, hipStream_t stream) {
+  hipLaunchKernelGGL(k_peak_partial, dim3(kPeakBlocks), dim3(256), 0, stream, c, K, scratch);
+  hipLaunchKernelGGL(k_peak_final, dim3(1), dim3(64), 0, stream, scratch, peak);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- host side
@@ -776,25 +1068,42 @@ void plan_tiles(int nbi, int nbj, TilePlan* t) {
     }
 }
 
+bool sym_patch_size(int nl, int nm) {
+  const int nbj = (nm + 15) / 16;
+  return (nl == 257 && nbj == 17) || (nl == 129 && nbj == 9) || (nl == 65 && nbj == 5);
+}
+
 template <int PREC>
 static hipError_t launch_family(const BatchArgs& a, dim3 grid, hipStream_t stream) {
   const TilePlan& t = a.src[0].tp;
+  if (a.src[0].sym) {
+    if (t.tbi[0] == 9 && t.tbi[1] == 8)
+      hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17, true>), grid, dim3(512), 0, stream, a);
+    else if (t.tbi[0] == 9)
+      hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9, true>), grid, dim3(512), 0, stream, a);
+    else if (t.tbi[0] == 5)
+      hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5, true>), grid, dim3(512), 0, stream, a);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (t.tbi[0] == 9 && t.tbi[1] == 8)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17, false>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 9)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9, false>), grid, dim3(512), 0, stream, a);
   else if (t.tbi[0] == 5)
-    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5, false>), grid, dim3(512), 0, stream, a);
   else
-    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8>), grid, dim3(512), 0, stream, a);
+    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8, false>), grid, dim3(512), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_patch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t stream) {
   if (a.n_src < 1 || a.n_src > kMaxBatch || n_wg < 1) return hipErrorInvalidValue;
-  for (int s = 1; s < a.n_src; ++s)  // one tile family per launch
+  for (int s = 1; s < a.n_src; ++s)  // one tile family and one form per launch
     if (a.src[s].tp.tbi[0] != a.src[0].tp.tbi[0] || a.src[s].tp.tbi[1] != a.src[0].tp.tbi[1] ||
-        a.src[s].tp.tbj[0] != a.src[0].tp.tbj[0] || a.src[s].tp.tbj[1] != a.src[0].tp.tbj[1])
+        a.src[s].tp.tbj[0] != a.src[0].tp.tbj[0] || a.src[s].tp.tbj[1] != a.src[0].tp.tbj[1] ||
+        a.src[s].sym != a.src[0].sym)
       return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(n_wg));
   switch (prec) {

@@ -85,7 +85,13 @@ int validate_src(const psf_src* s, int idx) {
 }
 
 int validate_prec(int prec) {
-  if (prec < PSF_FP32 || prec > PSF_PLAIN_BF16) return fail(PSF_EINVAL, "unknown precision %d", prec);
+  const int base = prec_base(prec);
+  if (base < PSF_FP32 || base > PSF_PLAIN_BF16) return fail(PSF_EINVAL, "unknown precision %d", prec);
+  return PSF_OK;
+}
+
+int reject_normalise(int prec, const char* entry) {
+  if (prec_normalise(prec)) return fail(PSF_EINVAL, "%s does not take PSF_NORMALISE", entry);
   return PSF_OK;
 }
 
@@ -111,29 +117,38 @@ ObsView view(const psf_obs* o) {
 // ------------------------------------------------------------------ planning
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Cost of one 16-visibility chunk of each tile type of a tile plan, in SIMD
-// cycles on MI355X: matrix-core time of the busiest SIMD's two waves plus
-// the vector time of its phase-factor rows (one A-row and one B-row wave,
-// about 10 instructions per row and 100 per chunk for seeds and records,
-// 4.7 cycles each).  Measured kernels behave closer to the sum of the two
-// than to their maximum.
-static void chunk_costs(const TilePlan& t, int prec, double cost[2][2]) {
+bool sym_source(const psf_src* s) { return sym_patch_size(s->nl, s->nm); }
+
+// Cost of one chunk (16 visibilities, 32 in the symmetric form) of each tile
+// type of a tile plan, in SIMD cycles on MI355X: matrix-core time of the
+// busiest SIMD's two waves plus the vector time of its phase-factor rows
+// (one A-row and one B-row wave, about 10 instructions per row and 100 per
+// chunk for seeds and records, twice that in the symmetric form, 4.7 cycles
+// each).  Measured kernels behave closer to the sum of the two than to their
+// maximum.
+static void chunk_costs(const TilePlan& t, int prec, bool sym, double cost[2][2]) {
   const double mfma_per_block = prec == PSF_FP32 ? 256.0 : prec == PSF_PLAIN_BF16 ? 16.0 : 48.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
-      const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c]);
-      const double gen = 4.7 * (10.0 * (t.tbi[r] + t.tbj[c]) + 100.0);
+      const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c], sym);
+      const double gen = 4.7 * (10.0 * (t.tbi[r] + t.tbj[c]) + (sym ? 200.0 : 100.0));
       cost[r][c] = mf + gen;
     }
+}
+
+static int64_t chunk_count(const psf_obs* o, bool sym) {
+  const int64_t ch = sym ? kPatchChunkSym : kPatchChunk;
+  return std::max<int64_t>(1, (o->K + ch - 1) / ch);
 }
 
 double patch_work(const psf_obs* o, const psf_src* s, int prec) {
   TilePlan t;
   plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
+  const bool sym = sym_source(s);
   double cost[2][2];
-  chunk_costs(t, prec, cost);
+  chunk_costs(t, prec, sym, cost);
   const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
-  const double chunks = static_cast<double>(std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk));
+  const double chunks = static_cast<double>(chunk_count(o, sym));
   double work = 0.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) work += static_cast<double>(cnt_i[r]) * cnt_j[c] * cost[r][c] * chunks;
@@ -144,16 +159,18 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
   PatchPlan p;
   TilePlan& t = p.tp;
   plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
-  const int64_t chunks = std::max<int64_t>(1, (o->K + kPatchChunk - 1) / kPatchChunk);
+  p.sym = sym_source(s);
+  const int64_t chunks = chunk_count(o, p.sym);
+  const int64_t ch = p.sym ? kPatchChunkSym : kPatchChunk;
   double cost[2][2];
-  chunk_costs(t, prec, cost);
+  chunk_costs(t, prec, p.sym, cost);
   // k-slices per tile so that every work item costs about item_work
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       int64_t n = static_cast<int64_t>(std::llround(cost[r][c] * static_cast<double>(chunks) / item_work));
       n = std::min<int64_t>(std::max<int64_t>(1, n), chunks);
       t.ns[r][c] = static_cast<int>(n);
-      t.kps[r][c] = ((chunks + n - 1) / n) * kPatchChunk;
+      t.kps[r][c] = ((chunks + n - 1) / n) * ch;
     }
   p.partial_elems = tile_plan_partial_elems(t);
   return p;
@@ -168,15 +185,18 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
   b += align_up(static_cast<size_t>(o->K) * sizeof(BinRec), 256);  // (u', v')
   b += align_up(static_cast<size_t>(o->K) * sizeof(float2), 256);   // c = W D
   b += align_up(p.partial_elems * sizeof(float), 256);
+  b += kPeakBytes;                                                   // a6 peak
   return b;
 }
 
 // ------------------------------------------------------------------ contraction
 SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec, const float2* c, float* partial,
-                 float* P, const double* dir) {
+                 float* P, const double* dir, const double* peak) {
   SrcPlan p;
+  p.peak = peak;
   p.tp = plan.tp;
   p.item0 = 0;
+  p.sym = plan.sym ? 1 : 0;
   p.rec = rec;
   p.c = c;
   p.partial = partial;
@@ -197,7 +217,11 @@ int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
   hipEvent_t ev0;
   hipError_t e;
   if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  e = launch_patch(prec, a, n_wg, s);
+  // a few bins: split-BF16's per-term error (3 2^-16 of a term) is not
+  // averaged away, so FP32 products run instead (same plan, negligible cost)
+  int kp = prec_base(prec);
+  if (kp == PSF_SPLIT_BF16 && a.K < kSmallK) kp = PSF_FP32;
+  e = launch_patch(kp, a, n_wg, s);
   if (e != hipSuccess) return hip_fail(e, "k_patch launch");
   if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");
   e = launch_finalize(a, s);
@@ -205,12 +229,12 @@ int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
 }
 
 int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const BinRec* rec,
-             const float2* c, float* partial, float* P, hipStream_t s) {
+             const float2* c, float* partial, float* P, hipStream_t s, const double* dir, const double* peak) {
   BatchArgs a;
   a.n_src = 1;
   a.flush_chunks = kFlushChunks;
   a.K = obs->K;
-  a.src[0] = src_plan(h_src, plan, rec, c, partial, P, nullptr);
+  a.src[0] = src_plan(h_src, plan, rec, c, partial, P, dir, peak);
   a.n_items = tile_plan_items(plan.tp);
   return run_batch(prec, a, a.n_items, s);
 }
@@ -304,6 +328,7 @@ int psf_workspace_bytes(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  prec = prec_base(prec);  // the normalisation's peak is part of every layout
   if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
   if (n_src < 1 || h_srcs == nullptr) return fail(PSF_EINVAL, "need n_src >= 1 sources");
   size_t need = 0;
@@ -355,6 +380,8 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_src(h_src, 0)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  const bool norm = prec_normalise(prec);
+  prec = prec_base(prec);
   if (P == nullptr) return fail(PSF_EINVAL, "P is NULL");
   const PatchPlan plan = plan_patch(obs, h_src, prec, kTargetWorkgroups);
   const size_t need = patch_workspace(obs, plan);
@@ -369,6 +396,8 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
   float2* c = reinterpret_cast<float2*>(w);
   w += align_up(static_cast<size_t>(obs->K) * sizeof(float2), 256);
   float* partial = reinterpret_cast<float*>(w);
+  w += align_up(plan.partial_elems * sizeof(float), 256);
+  double* peak = reinterpret_cast<double*>(w);  // [0]: the peak; [1..]: its reduction scratch
 
   hipError_t e = hipSuccess;
   if (obs->K > 0) {
@@ -376,7 +405,8 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
                       nullptr, rec, c, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
   }
-  return contract(obs, h_src, plan, prec, rec, c, partial, P, s);
+  if (norm && (e = launch_peak(c, obs->K, peak + 1, peak, s)) != hipSuccess) return hip_fail(e, "peak launch");
+  return contract(obs, h_src, plan, prec, rec, c, partial, P, s, nullptr, norm ? peak : nullptr);
 }
 
 }  // extern "C"

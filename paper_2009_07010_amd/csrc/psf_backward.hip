@@ -24,7 +24,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_grad_reduce(const float* __r
                                                                 const float* __restrict__ Pe, int nl, int nm,
                                                                 double l_first, double dl, double l0,
                                                                 double m_first, double dm, double m0,
+                                                                const double* __restrict__ dir,
                                                                 double* __restrict__ grad) {
+  if (dir != nullptr) {  // direction and grid from device memory (psf_src layout)
+    l0 = dir[0];
+    m0 = dir[1];
+    l_first = dir[2];
+    m_first = dir[3];
+    dl = dir[4];
+    dm = dir[5];
+  }
   const int64_t n = static_cast<int64_t>(nl) * nm;
   double gl = 0.0, gm = 0.0;
   for (int64_t p = threadIdx.x; p < n; p += kReduceThreads) {
@@ -59,9 +68,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_grad_reduce(const float* __r
 }
 
 hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, double l_first, double dl,
-                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream) {
+                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream,
+                              const double* dir) {
   hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(kReduceThreads), 0, stream, G, Pe, nl, nm, l_first, dl, l0,
-                     m_first, dm, m0, grad);
+                     m_first, dm, m0, dir, grad);
   return hipGetLastError();
 }
 
@@ -168,10 +178,10 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
                                   const float* G_all, int prec, double* grad_lm, void* ws, size_t ws_bytes,
                                   void* stream) {
   clear_error();
-  (void)d_srcs;
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = reject_normalise(prec, "psf_patch_backward")) != PSF_OK) return st;
   if (n_src < 1 || h_srcs == nullptr) return fail(PSF_EINVAL, "need n_src >= 1 sources");
   for (int s = 0; s < n_src; ++s)
     if ((st = validate_src(&h_srcs[s], s)) != PSF_OK) return st;
@@ -190,22 +200,26 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
   const int64_t K = obs->K;
   for (int n = 0; n < n_src; ++n) {
     const psf_src& src = h_srcs[n];
+    // directions and grids from the device array when given (read at run
+    // time, so a captured call replays for new directions)
+    const double* dir = d_srcs != nullptr ? reinterpret_cast<const double*>(d_srcs + n) : nullptr;
     const int64_t pix = static_cast<int64_t>(src.nl) * src.nm;
     hipError_t e;
     if (K > 0) {
-      e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, nullptr, coef, s);
+      e = launch_decorr(view(obs), src.l0, src.m0, src.dl, src.dm, nullptr, nullptr, rec, nullptr, coef, s, dir);
       if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
     }
     if (adjoint_reverse_ok(prec, obs, src)) {
-      e = launch_adjoint_reverse(obs, src, prec, rec, coef, G_all + src.out_off, adj, grad_lm + 2 * n, s);
+      e = launch_adjoint_reverse(obs, src, prec, rec, coef, G_all + src.out_off, adj, grad_lm + 2 * n, s, dir);
       if (e != hipSuccess) return hip_fail(e, "k_adjoint launch");
       continue;
     }
     const PatchPlan plan = plan_patch(obs, &src, prec, kTargetWorkgroups);
     for (int q = 0; q < 5; ++q)
-      if ((st = contract(obs, &src, plan, prec, rec, coef + q * K, partial, pe + q * pix, s)) != PSF_OK) return st;
+      if ((st = contract(obs, &src, plan, prec, rec, coef + q * K, partial, pe + q * pix, s, dir)) != PSF_OK)
+        return st;
     e = launch_grad_reduce(G_all + src.out_off, pe, src.nl, src.nm, src.l_first, src.dl, src.l0, src.m_first,
-                           src.dm, src.m0, grad_lm + 2 * n, s);
+                           src.dm, src.m0, grad_lm + 2 * n, s, dir);
     if (e != hipSuccess) return hip_fail(e, "k_grad_reduce launch");
   }
   return PSF_OK;

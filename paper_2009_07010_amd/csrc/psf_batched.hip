@@ -36,17 +36,19 @@ const int kFlushCandidates[] = {32, 64, 128};
 const int kItemsCandidates[] = {1, 2, 3, 4};
 constexpr int kMaxItemsPerCU = 4;  // the largest candidate: bounds the workspace
 
+// Tile family and form (general or symmetric) of a source: the sources of
+// one contraction launch share both.
 struct Family {
-  int tbi0, tbi1, tbj0, tbj1;
+  int tbi0, tbi1, tbj0, tbj1, sym;
   bool operator==(const Family& o) const {
-    return tbi0 == o.tbi0 && tbi1 == o.tbi1 && tbj0 == o.tbj0 && tbj1 == o.tbj1;
+    return tbi0 == o.tbi0 && tbi1 == o.tbi1 && tbj0 == o.tbj0 && tbj1 == o.tbj1 && sym == o.sym;
   }
 };
 
 Family family_of(const psf_src& s) {
   TilePlan t;
   plan_tiles((s.nl + 15) / 16, (s.nm + 15) / 16, &t);
-  return {t.tbi[0], t.tbi[1], t.tbj[0], t.tbj[1]};
+  return {t.tbi[0], t.tbi[1], t.tbj[0], t.tbj[1], sym_source(&s) ? 1 : 0};
 }
 
 struct Tuning {
@@ -56,8 +58,8 @@ struct Tuning {
 };
 
 // Reads the table psf_autotune writes: a JSON object whose "families" array
-// holds objects with integer fields tbi0, tbi1, tbj0, tbj1, items_per_cu and
-// flush.  Only that shape is accepted.
+// holds objects with integer fields tbi0, tbi1, tbj0, tbj1, items_per_cu,
+// flush and (optional, default 0) sym.  Only that shape is accepted.
 int parse_tuning(const char* json, std::vector<Tuning>* out) {
   out->clear();
   if (json == nullptr) return PSF_OK;
@@ -83,6 +85,7 @@ int parse_tuning(const char* json, std::vector<Tuning>* out) {
         !field(o, oe, "tbj0", &t.fam.tbj0) || !field(o, oe, "tbj1", &t.fam.tbj1) ||
         !field(o, oe, "items_per_cu", &t.items_per_cu) || !field(o, oe, "flush", &t.flush))
       return fail(PSF_EINVAL, "tuning table: entry lacks a field");
+    if (!field(o, oe, "sym", &t.fam.sym)) t.fam.sym = 0;
     if (t.items_per_cu < 1 || t.items_per_cu > kMaxItemsPerCU || t.flush < 1 || t.flush > 4096)
       return fail(PSF_EINVAL, "tuning table: items_per_cu (1..%d) or flush (1..4096) out of range", kMaxItemsPerCU);
     out->push_back(t);
@@ -94,8 +97,8 @@ int parse_tuning(const char* json, std::vector<Tuning>* out) {
 // the MeerKAT-shaped data (one for the 257- and 129-pixel families, whose
 // items are large; three for the 65-pixel family), two otherwise.
 int default_items_per_cu(const Family& f) {
-  if (f == Family{9, 8, 17, 17} || f == Family{9, 9, 9, 9}) return 1;
-  if (f == Family{5, 5, 5, 5}) return 3;
+  if (f.tbi0 == 9 && (f.tbi1 == 8 || f.tbi1 == 9)) return 1;
+  if (f.tbi0 == 5 && f.tbi1 == 5 && f.tbj0 == 5) return 3;
   return kDefaultItemsPerCU;
 }
 constexpr int kMaxDefaultItemsPerCU = 3;
@@ -166,7 +169,8 @@ size_t records_bytes(const psf_obs* o) {
 }
 
 // Workspace: [records of up to group_capacity sources][partial slabs of the
-// largest group, for the largest items-per-CU a tuning table may ask].
+// largest group, for the largest items-per-CU a tuning table may ask][the
+// normalisation peaks of up to kMaxBatch sources].
 size_t batch_workspace_for(const psf_obs* o, int n_src, const psf_src* h, int prec, int max_items_per_cu) {
   const std::vector<Group> groups = make_groups(o, n_src, h);
   size_t rec = 0, part = 0;
@@ -174,11 +178,11 @@ size_t batch_workspace_for(const psf_obs* o, int n_src, const psf_src* h, int pr
     rec = std::max(rec, g.idx.size() * records_bytes(o));
     part = std::max(part, plan_group(o, h, g, prec, max_items_per_cu).partial_elems * sizeof(float));
   }
-  return align_up(rec, 256) + align_up(part, 256);
+  return align_up(rec, 256) + align_up(part, 256) + kMaxBatch * kPeakBytes;
 }
 
-int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* d, int prec,
-                const std::vector<Tuning>& table, float* P_all, void* ws, hipStream_t st) {
+int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* d, int prec, bool norm,
+                const std::vector<Tuning>& table, float* P_all, void* ws, hipStream_t st, size_t peak_off) {
   const std::vector<Group> groups = make_groups(obs, n_src, h);
   const size_t rec = records_bytes(obs);
   size_t rec_area = 0;
@@ -206,7 +210,13 @@ int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* 
         hipError_t e = launch_decorr_sources(ov, dir, 0, 1, rec, c, 0, st);
         if (e != hipSuccess) return hip_fail(e, "k_decorr launch");
       }
-      a.src[q] = src_plan(&h[s], gp.plans[q], rec, c, partial + poff, P_all + h[s].out_off, dir);
+      double* peak = reinterpret_cast<double*>(base + peak_off + q * kPeakBytes);
+      if (norm) {
+        hipError_t e = launch_peak(c, obs->K, peak + 1, peak, st);
+        if (e != hipSuccess) return hip_fail(e, "peak launch");
+      }
+      a.src[q] = src_plan(&h[s], gp.plans[q], rec, c, partial + poff, P_all + h[s].out_off, dir,
+                          norm ? peak : nullptr);
       a.src[q].item0 = item0;
       item0 += tile_plan_items(gp.plans[q].tp);
       poff += align_up(gp.plans[q].partial_elems, 64);
@@ -257,6 +267,8 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, 
   clear_error();
   int st;
   if ((st = validate_batch(obs, n_src, h_srcs, prec)) != PSF_OK) return st;
+  const bool norm = prec_normalise(prec);
+  prec = prec_base(prec);
   if (d_srcs == nullptr || P_all == nullptr) return fail(PSF_EINVAL, "d_srcs or P_all is NULL");
   std::vector<Tuning> table;
   if ((st = parse_tuning(tuning_json, &table)) != PSF_OK) return st;
@@ -266,7 +278,8 @@ int psf_patch_batched(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, 
   if (ws == nullptr || ws_bytes < need)
     return fail(PSF_EWORKSPACE, "psf_patch_batched needs %zu workspace bytes, got %zu", need, ws_bytes);
   if ((st = check_device()) != PSF_OK) return st;
-  return run_batched(obs, n_src, h_srcs, d_srcs, prec, table, P_all, ws, static_cast<hipStream_t>(stream));
+  return run_batched(obs, n_src, h_srcs, d_srcs, prec, norm, table, P_all, ws, static_cast<hipStream_t>(stream),
+                     need - kMaxBatch * kPeakBytes);
 }
 
 int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int prec, void* ws, size_t ws_bytes,
@@ -274,6 +287,7 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
   clear_error();
   int st;
   if ((st = validate_batch(obs, n_src, h_srcs, prec)) != PSF_OK) return st;
+  prec = prec_base(prec);  // normalisation does not change the launch shapes
   if (json_out == nullptr || json_cap < 64) return fail(PSF_EINVAL, "json_out missing or too small");
   if ((st = check_device()) != PSF_OK) return st;
   const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -365,10 +379,10 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
     if (rc != PSF_OK) break;
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "%s{\"tbi0\": %d, \"tbi1\": %d, \"tbj0\": %d, \"tbj1\": %d, \"items_per_cu\": %d, "
-                  "\"flush\": %d, \"ms\": %.4f, \"nl\": %d, \"nm\": %d}",
-                  f ? ", " : "", fams[f].tbi0, fams[f].tbi1, fams[f].tbj0, fams[f].tbj1, best_ipc, best_flush,
-                  best_ms, src.nl, src.nm);
+                  "%s{\"tbi0\": %d, \"tbi1\": %d, \"tbj0\": %d, \"tbj1\": %d, \"sym\": %d, "
+                  "\"items_per_cu\": %d, \"flush\": %d, \"ms\": %.4f, \"nl\": %d, \"nm\": %d}",
+                  f ? ", " : "", fams[f].tbi0, fams[f].tbi1, fams[f].tbj0, fams[f].tbj1, fams[f].sym, best_ipc,
+                  best_flush, best_ms, src.nl, src.nm);
     out += buf;
   }
   (void)hipEventDestroy(e0);

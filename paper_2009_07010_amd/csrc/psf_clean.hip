@@ -139,6 +139,7 @@ int validate_clean(const psf_obs* obs, const psf_src* grid, int prec) {
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = reject_normalise(prec, "psf_clean_hogbom")) != PSF_OK) return st;
   if ((st = validate_src(grid, 0)) != PSF_OK) return st;
   return PSF_OK;
 }

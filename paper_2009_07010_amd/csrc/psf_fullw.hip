@@ -204,6 +204,7 @@ int psf_patch_fullw(const psf_obs* obs, const psf_src* h_src, int prec, float* P
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_src(h_src, 0)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = reject_normalise(prec, "psf_patch_fullw")) != PSF_OK) return st;
   if (P == nullptr) return fail(PSF_EINVAL, "P is NULL");
   double q_lo = 0.0;
   if ((st = fullw_grid(h_src, &q_lo)) != PSF_OK) return st;

@@ -15,11 +15,19 @@ constexpr int kTargetWorkgroups = 256;
 // First-level accumulation run of the contraction: 128 chunks of 16
 // visibilities (2048 terms per pixel) before folding into the second level.
 constexpr int kFlushChunks = 128;
+// Below this many bins the split-BF16 contraction runs as FP32.
+constexpr int64_t kSmallK = 256;
 
 struct PatchPlan {
   TilePlan tp;
   size_t partial_elems;
+  bool sym;  // symmetric form of the contraction (see k_patch.hip)
 };
+
+// Whether a source's contraction runs in the symmetric form: a patch size
+// with a compiled symmetric form (any grid position: the offset of the
+// grid's centre row from the source joins the coefficients).
+bool sym_source(const psf_src* s);
 
 int fail(int status, const char* fmt, ...);
 // Clears the thread's last-error message (every entry point starts with it).
@@ -28,7 +36,14 @@ int hip_fail(hipError_t e, const char* what);
 int check_device();
 int validate_obs(const psf_obs* o);
 int validate_src(const psf_src* s, int idx);
+// Accepts the arithmetic with or without PSF_NORMALISE (entry points that
+// cannot normalise check the flag themselves); prec_base strips the flag.
 int validate_prec(int prec);
+inline int prec_base(int prec) { return prec & ~PSF_NORMALISE; }
+inline bool prec_normalise(int prec) { return (prec & PSF_NORMALISE) != 0; }
+int reject_normalise(int prec, const char* entry);
+// Workspace bytes of one source's peak (a6) and its reduction scratch.
+constexpr size_t kPeakBytes = 256 * ((8 * (kPeakBlocks + 1) + 255) / 256);
 ObsView view(const psf_obs* o);
 size_t align_up(size_t x, size_t a);
 // Matrix-core / generator cost of a source's whole patch (SIMD cycles).
@@ -41,11 +56,14 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 
 // The contraction and finalise of one patch from per-bin records (u', v')
 // and coefficients c (c_k = W_k D_k for the patch itself).
+// dir (optional): the source's direction and grid in device memory
+// (psf_src layout), read at run time instead of h_src's.
 int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const BinRec* rec,
-             const float2* c, float* partial, float* P, hipStream_t s);
+             const float2* c, float* partial, float* P, hipStream_t s, const double* dir = nullptr,
+             const double* peak = nullptr);
 
 SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec, const float2* c, float* partial,
-                 float* P, const double* dir);
+                 float* P, const double* dir, const double* peak = nullptr);
 // Contraction (n_wg persistent workgroups) and finalise of the sources of a.
 int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s);
 
@@ -59,7 +77,7 @@ bool adjoint_reverse_ok(int prec, const psf_obs* o, const psf_src& s);
 size_t adjoint_reverse_partial_bytes();
 hipError_t launch_adjoint_reverse(const psf_obs* o, const psf_src& s, int prec, const BinRec* rec,
                                   const float2* coef, const float* G, double* partial, double* grad,
-                                  hipStream_t st);
+                                  hipStream_t st, const double* dir = nullptr);
 
 bool timing_on();
 hipError_t timed_launch_begin(hipStream_t s, hipEvent_t* ev0);

@@ -53,10 +53,18 @@ struct TilePlan {
 struct SrcPlan {
   TilePlan tp;
   int64_t item0;
+  // 1: the patch is 65, 129 or 257 rows high and the contraction runs in
+  // its symmetric form (rows of cos and sin of the non-negative half of the
+  // row offsets from the grid's centre row, inner dimension K; see
+  // k_patch.hip).  Every source of a launch agrees.
+  int sym;
   const BinRec* rec;  // [K] per-bin records
   const float2* c;     // [K] W_k D_k (or an adjoint coefficient vector)
   float* partial;      // partial slabs, see TilePlan
   float* P;            // output patch [nl][nm]
+  // If not null: the patch's value at the source, 2 Re sum_k c_k (FP64,
+  // written by launch_peak before the finalise), which divides the output.
+  const double* peak;
   // Source direction and pixel grid: read at run time from `dir` (device
   // memory laid out as psf_src: l0, m0, l_first, m_first, dl, dm) when it
   // is not null, else taken from the fields below.
@@ -75,7 +83,8 @@ struct BatchArgs {
   SrcPlan src[kMaxBatch];
 };
 
-constexpr int kPatchChunk = 16;  // visibilities per contraction chunk
+constexpr int kPatchChunk = 16;     // visibilities per contraction chunk
+constexpr int kPatchChunkSym = 32;  // visibilities per chunk of the symmetric form
 
 // Power-of-two scale of the adjoint coefficient vectors (keeps them inside
 // the FP16 range; exact in every precision).
@@ -83,8 +92,12 @@ constexpr double kAdjointScale = 1.0 / 4096.0;
 
 // coef_out (optional, [5][K]): the adjoint coefficient vectors e0..e4 (see
 // k_decorr.hip) times kAdjointScale; needs D_in == nullptr.
+// dir (optional): device memory laid out as psf_src (l0, m0, l_first,
+// m_first, dl, dm) from which the direction and cells are read at run time
+// instead of l0, m0, dl, dm.
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
-                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream);
+                         float2* D_out, BinRec* rec_out, float2* c_out, float2* coef_out, hipStream_t stream,
+                         const double* dir = nullptr);
 // Method-1 (sinc) decorrelation factors, written as (D, 0).
 hipError_t launch_decorr_sinc(const ObsView& o, double l0, double m0, float2* D_out, hipStream_t stream);
 // Records of n_src sources in one launch: source y's direction and grid are
@@ -97,20 +110,32 @@ hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t d
 // patches Pe [5][nl][nm] of the coefficient vectors e0..e4, FP64, written
 // to grad[0..1].
 hipError_t launch_grad_reduce(const float* G, const float* Pe, int nl, int nm, double l_first, double dl,
-                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream);
+                              double l0, double m_first, double dm, double m0, double* grad, hipStream_t stream,
+                              const double* dir = nullptr);
 
 // Tile shapes of the compiled contraction for a patch of nbi x nbj blocks;
 // fills tbi, tbj and the tile counts of *tp (not ns / kps).
 void plan_tiles(int nbi, int nbj, TilePlan* tp);
+// Whether a patch of nl x nm pixels has a compiled symmetric form (nl is
+// 65, 129 or 257 and nm falls in the same tile family).
+bool sym_patch_size(int nl, int nm);
 // Blocks of the busiest SIMD (its two contraction waves) of a tbi x tbj tile.
-int tile_max_simd_blocks(int tbi, int tbj);
+int tile_max_simd_blocks(int tbi, int tbj, bool sym);
 size_t tile_plan_partial_elems(const TilePlan& tp);
 // Work items of one source's tile plan.
 int64_t tile_plan_items(const TilePlan& tp);
 // Contraction of every item of `a` with `grid` persistent workgroups (each
 // takes items blockIdx.x, blockIdx.x + grid, ...).
 hipError_t launch_patch(int prec, const BatchArgs& a, int64_t grid, hipStream_t stream);
-// P = 2 * (sum of the k-slices) for every source of `a`.
+// P = 2 * (sum of the k-slices) for every source of `a` (divided by the
+// source's peak where SrcPlan::peak is set).
 hipError_t launch_finalize(const BatchArgs& a, hipStream_t stream);
+
+// Normalisation [section 4: errors are taken on PSFs normalised at the
+// source]: peak = 2 Re sum_k c_k of one source, FP64, summed in a fixed
+// order (kPeakBlocks contiguous ranges, then their partial sums in order).
+// scratch holds kPeakBlocks doubles.
+constexpr int kPeakBlocks = 512;
+hipError_t launch_peak(const float2* c, int64_t K, double* scratch, double* peak, hipStream_t stream);
 
 }  // namespace psf

@@ -173,6 +173,7 @@ int psf_method2_workspace_bytes(const psf_obs* obs, int32_t N, int prec, int32_t
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = reject_normalise(prec, "psf_method2")) != PSF_OK) return st;
   if ((st = validate_grid(N, 1e-6)) != PSF_OK) return st;
   if (n_src < 0) return fail(PSF_EINVAL, "n_src < 0");
   if (out == nullptr) return fail(PSF_EINVAL, "out is NULL");
@@ -188,6 +189,7 @@ int psf_method2_spectrum(const psf_obs* obs, int32_t N, double cell, int prec, f
   int st;
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if ((st = reject_normalise(prec, "psf_method2")) != PSF_OK) return st;
   if ((st = validate_grid(N, cell)) != PSF_OK) return st;
   if (S == nullptr) return fail(PSF_EINVAL, "S is NULL");
   const psf_src g = effective_grid(N, cell);

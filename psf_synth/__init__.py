@@ -206,25 +206,34 @@ def bin_tables(n_t: int, n_ch: int, bl_bin: np.ndarray):
 
 def bin_centre_uvw(bl_enu: np.ndarray, times: np.ndarray, uvw_m: np.ndarray,
                    bl_bin: np.ndarray, lat: float, dec: float) -> np.ndarray:
-    """Earth-rotation uvw at the mean time of every time bin, [n_tb, 3]."""
+    """Earth-rotation uvw at the mean time of every time bin, [n_tb, 3].
+
+    Baselines sharing a bin length are done together: the mean time of
+    each full bin is a row mean of the reshaped time axis (the same sum as
+    the mean of the slice), the short last bin is averaged on its own.
+    """
     n_t = times.shape[0]
-    rows = []
-    for b in range(bl_enu.shape[0]):
-        nt = int(bl_bin[b, 0])
-        n_tb = -(-n_t // nt)
+    nts = bl_bin[:, 0].astype(np.int64)
+    off = np.zeros(len(nts) + 1, np.int64)
+    off[1:] = np.cumsum(-(-n_t // nts))
+    out = np.empty((int(off[-1]), 3))
+    for nt in np.unique(nts):
+        nt = int(nt)
+        bls = np.nonzero(nts == nt)[0]
+        n_tb, n_full = -(-n_t // nt), n_t // nt
         t_centre = np.empty(n_tb)
-        single = np.zeros(n_tb, bool)
-        for T in range(n_tb):
-            t0, t1 = T * nt, min(n_t, (T + 1) * nt)
-            t_centre[T] = np.mean(times[t0:t1])
-            single[T] = (t1 - t0) == 1
-        uc = uvw_tracks(bl_enu[b:b + 1], OMEGA_EARTH * t_centre, lat, dec)[0]
+        t_centre[:n_full] = np.mean(times[:n_full * nt].reshape(n_full, nt), axis=1)
+        if n_tb > n_full:
+            t_centre[n_full] = np.mean(times[n_full * nt:])
+        uc = uvw_tracks(bl_enu[bls], OMEGA_EARTH * t_centre, lat, dec)    # [n, n_tb, 3]
+        single = np.minimum(n_t, (np.arange(n_tb) + 1) * nt) - np.arange(n_tb) * nt == 1
         if single.any():
             # one-sample bins: the centre is the sample itself, bit for bit
             idx = np.nonzero(single)[0]
-            uc[idx] = uvw_m[b, idx * nt]
-        rows.append(uc)
-    return np.concatenate(rows, axis=0)
+            uc[:, idx] = uvw_m[bls][:, idx * nt]
+        for q, b in enumerate(bls):
+            out[off[b]:off[b + 1]] = uc[q]
+    return out
 
 
 def bin_centre_uvw_uniform(bl_enu: np.ndarray, times: np.ndarray, uvw_m: np.ndarray,

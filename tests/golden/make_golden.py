@@ -136,6 +136,40 @@ def config5():
                "columns: source index, i, j, P_ij, peak 2 Re sum W D")
 
 
+def config5_far_sources():
+    """The source of each patch size of workload 5 at the largest radius
+    (where the phase factors turn fastest and the split forms' errors peak)."""
+    srcs = ps.sources(5, seed=0)
+    idx = []
+    for n in (65, 129, 257):
+        cand = [i for i, s in enumerate(srcs) if s.nl == n]
+        idx.append(max(cand, key=lambda i: np.hypot(srcs[i].l0, srcs[i].m0)))
+    return idx
+
+
+def config5_far():
+    """Workload 5 at sampled pixels of the largest-radius source of each
+    patch size (65, 129, 257), FP64, with each patch's peak."""
+    obs = ps.observation(5, seed=0)
+    srcs = ps.sources(5, seed=0)
+    idx = config5_far_sources()
+    pix = config5_pixels([srcs[i] for i in idx], 24)
+    t = time.time()
+    rows = []
+    for i, ij in zip(idx, pix):
+        D = orc.decorr(obs, srcs[i].l0, srcs[i].m0)
+        P = orc.patch_pixels(obs, srcs[i], ij[:, 0], ij[:, 1], D)
+        peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+        rows += [(i, a, b, v, peak) for (a, b), v in zip(ij, P)]
+        print("config5 far source", i, time.time() - t, flush=True)
+    np.save(os.path.join(HERE, "config5_seed0_far_pixels.npy"), np.array(rows, dtype=np.float64))
+    _meta("config5_seed0_far", config=5, seed=0, K=obs.K, sources=idx,
+          radii_deg=[float(np.degrees(np.arcsin(np.hypot(srcs[i].l0, srcs[i].m0)))) for i in idx],
+          seconds=time.time() - t,
+          what="oracle.patch_pixels (FP64) at sampled pixels of the largest-radius source of each patch "
+               "size of workload 5; columns: source index, i, j, P_ij, peak 2 Re sum W D")
+
+
 CONFIG4_SOURCES = [5, 7, 0, 2]    # radii 0.45, 1.67, 1.87, 2.8 deg
 
 

@@ -102,9 +102,9 @@ def test_workspace_too_small(L):
     srcs = (pk.PsfSrc * 1)(s)
     need = ctypes.c_size_t(0)
     assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, 1, ctypes.byref(need)) == 0
-    assert need.value > 12 * 24
-    # the reported size covers every entry point; the records alone (24 B per
-    # bin) already exceed 12 * 24 - 1 bytes
+    assert need.value > 12 * 40
+    # the reported size covers every entry point; the records alone (40 B per
+    # bin and source: u', v', two step factors, W D) already exceed 12 * 24 - 1 bytes
     st, msg = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, FAKE, 12 * 24 - 1, None)
     assert st == pk.PSF_EWORKSPACE and "workspace" in msg
     st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1, FAKE, None, need.value, None)
@@ -248,3 +248,26 @@ def test_flux_entry_points_host_side_errors(L):
     assert L.psf_flux_scale(2, 10, None, FAKE, FAKE, None) == pk.PSF_EINVAL
     assert L.psf_flux_backward(2, 10, FAKE, FAKE, FAKE, FAKE, None, None) == pk.PSF_EINVAL
     assert L.psf_flux_backward(70000, 10, FAKE, FAKE, FAKE, FAKE, FAKE, None) == pk.PSF_EINVAL
+
+
+def test_normalise_flag(L):
+    """PSF_NORMALISE is accepted where the normalised PSF is produced (and by
+    the workspace query, whose size it does not change) and rejected by the
+    entry points that do not produce it, before anything is launched."""
+    o, s = fake_obs(), fake_src()
+    srcs = (pk.PsfSrc * 1)(s)
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, 1, ctypes.byref(a)) == 0
+    assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, 1 | pk.PSF_NORMALISE, ctypes.byref(b)) == 0
+    assert a.value == b.value
+    st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 1 | pk.PSF_NORMALISE, FAKE, FAKE, 1, None)
+    assert st == pk.PSF_EWORKSPACE  # the flag passed validation
+    st, _ = status_of(L.psf_patch, ctypes.byref(o), ctypes.byref(s), None, 0x200 | 1, FAKE, FAKE, 1, None)
+    assert st == pk.PSF_EINVAL
+    st, msg = status_of(L.psf_patch_backward, ctypes.byref(o), 1, srcs, None, FAKE, 1 | pk.PSF_NORMALISE, FAKE,
+                        FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL and "PSF_NORMALISE" in msg
+    n = ctypes.c_int32(0)
+    st, msg = status_of(L.psf_patch_fullw, ctypes.byref(o), ctypes.byref(s), 1 | pk.PSF_NORMALISE, FAKE,
+                        ctypes.byref(n), FAKE, 1 << 40, None)
+    assert st == pk.PSF_EINVAL and "PSF_NORMALISE" in msg

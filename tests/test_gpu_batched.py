@@ -3,6 +3,7 @@ sizes per call, persistent contraction, graph capture, autotuner) against
 the FP64 oracle.  Bar: 1e-5 peak-normalised max error per patch."""
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -190,4 +191,57 @@ def test_batched_config5_sampled_pixels(pk, config5, prec):
         got = parts[q].cpu().numpy().astype(np.float64)[ii, jj]
         e = np.max(np.abs(got - ref)) / abs(peak)
         print(f"config5 {prec} source {i} ({srcs[q].nl}^2): {e:.2e}", flush=True)
+        assert e <= TOL
+
+
+def _config5_gold():
+    """Stored FP64 pixels of workload 5: {source index: (i, j, P_ij, peak)}."""
+    out = {}
+    for name in ("config5_seed0_pixels.npy", "config5_seed0_far_pixels.npy"):
+        f = os.path.join(GOLD, name)
+        if not os.path.exists(f):
+            continue
+        rows = np.load(f)
+        for i in np.unique(rows[:, 0]).astype(int):
+            sel = rows[:, 0] == i
+            out[int(i)] = (rows[sel, 1].astype(int), rows[sel, 2].astype(int), rows[sel, 3], rows[sel, 4][0])
+    return out
+
+
+def test_batched_config5_all_256_sources_one_graph(pk, config5):
+    """Workload 5 at full size, every one of its 256 sources (65, 129 and
+    257 pixels a side, 0.05-3 deg) in one psf_patch_batched call captured
+    into a HIP graph; the replay's patches of every source with stored FP64
+    pixels (the first of each size, and the largest radius of each size)
+    against the oracle, peak-normalised."""
+    obs = config5
+    srcs = ps.sources(5, seed=0)
+    assert len(srcs) == 256
+    gold = _config5_gold()
+    dobs = pk.DeviceObservation(obs)
+    ws = pk.Workspace()
+    ws.get(pk.workspace_bytes(dobs, srcs, "split_bf16"))
+    _, d = pk.device_sources(srcs)
+    out = torch.full((sum(s.nl * s.nm for s in srcs),), float("nan"), dtype=torch.float32, device="cuda")
+    first = [next(s for s in srcs if s.nl == n) for n in (65, 129, 257)]
+    pk.patch_batched(dobs, first, workspace=ws)  # every tile family's kernels loaded outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.patch_batched(dobs, srcs, out=out, workspace=ws, d_srcs=d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    terms = float(obs.K) * sum(s.nl * s.nm for s in srcs)
+    print(f"workload 5, 256 sources in one graph replay: {wall:.2f} s, {terms / wall:.3e} terms/s", flush=True)
+    assert torch.isfinite(out).all()
+    parts = pk.split_patches(out, srcs)
+    assert len(gold) >= 3
+    for i, (ii, jj, ref, peak) in sorted(gold.items()):
+        got = parts[i].cpu().numpy().astype(np.float64)[ii, jj]
+        e = np.max(np.abs(got - ref)) / abs(peak)
+        r = np.degrees(np.arcsin(np.hypot(srcs[i].l0, srcs[i].m0)))
+        print(f"workload 5 source {i} ({srcs[i].nl}^2 at {r:.2f} deg): {e:.2e}", flush=True)
         assert e <= TOL

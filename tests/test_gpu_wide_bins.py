@@ -3,10 +3,10 @@ channels per bin, with a ragged last bin per baseline): the decorrelation
 factors (boxcar and windowed), the patch, and the adjoint's gradient against
 the FP64 oracle.  Bars: D within 2e-6, patches 1e-5 of the peak, gradients
 1e-4.  D is checked on a 200 MHz band where the bins decorrelate strongly;
-the patches and gradients on a 40 MHz band (mean |D| about 0.84), where the
-patch has a coherent peak: with only 120 bins and |D| near 0.1 the peak is
-no larger than a few terms, and split-BF16's per-term rounding (about 2^-17
-of a term) is then what a peak-normalised error measures."""
+the patches on a 40 MHz band (mean |D| about 0.84) and a 100 MHz band (the
+peak a small fraction of the sum of the term sizes, where split-BF16's
+per-term rounding of about 2^-17 of a term averages least), the gradients
+on the 40 MHz band."""
 import numpy as np
 import pytest
 
@@ -28,8 +28,8 @@ def pk():
     return pk
 
 
-def _obs(windowed, nu_lo=1.3e9, nu_hi=1.5e9):
-    obs = ps.tiny_random(41, n_ant=6, n_t=12, n_ch=37, nt=3, nc=19, radius_m=4000.0, nu_lo=nu_lo, nu_hi=nu_hi)
+def _obs(windowed, nu_lo=1.3e9, nu_hi=1.5e9, n_ant=6):
+    obs = ps.tiny_random(41, n_ant=n_ant, n_t=12, n_ch=37, nt=3, nc=19, radius_m=4000.0, nu_lo=nu_lo, nu_hi=nu_hi)
     return ps.tapered_windows(obs, strength=0.8) if windowed else obs
 
 
@@ -48,13 +48,21 @@ def test_wide_bin_decorr(pk, windowed):
 
 @pytest.mark.parametrize("windowed", [False, True])
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
-def test_wide_bin_patch(pk, windowed, prec):
-    obs = _obs(windowed, 1.38e9, 1.42e9)
+@pytest.mark.parametrize("band,n_ant", [((1.38e9, 1.42e9), 6), ((1.35e9, 1.45e9), 6), ((1.35e9, 1.45e9), 10)])
+def test_wide_bin_patch(pk, windowed, prec, band, n_ant):
+    """40 MHz (mean |D| about 0.84) and 100 MHz bands (strong decorrelation:
+    the peak is a small fraction of the sum of the term sizes), with 120 bins
+    (below 256: split-BF16 requests run FP32 products) and 360 bins (split
+    products)."""
+    obs = _obs(windowed, band[0], band[1], n_ant)
     src = ps.Source.centred(0.0021, -0.0013, 33, 2.0 * ps.ARCSEC)
-    P = orc.patch_factored(obs, src)
+    D = orc.decorr(obs, src.l0, src.m0)
+    P = orc.patch_factored(obs, src, D)
     Pg = pk.patch(pk.DeviceObservation(obs), src, prec=prec).double().cpu().numpy()
     err = orc.peak_normalised_error(Pg, P)[0]
-    print(f"wide bins windowed={windowed} {prec}: {err:.2e}", flush=True)
+    ratio = np.max(np.abs(P)) / (2.0 * np.sum(obs.W * np.abs(D)))
+    print(f"wide bins {band[1] - band[0]:.0e} Hz K={obs.K} windowed={windowed} {prec}: {err:.2e} "
+          f"(mean |D| {np.mean(np.abs(D)):.2f}, peak / sum of term sizes {ratio:.2f})", flush=True)
     assert err < TOL
 
 

@@ -206,6 +206,24 @@ def test_peak_equals_sum_of_weighted_D(cfg1):
     assert P[c, c] == pytest.approx(P.max(), rel=1e-12)
 
 
+def test_normalised_patch(cfg1):
+    """Row a6: the normalised PSF is 1 at the source pixel of a centred grid;
+    on a grid that does not hold the source it equals the brute-force patch
+    (explicit conjugate halves) divided by the brute-force value of a 1 x 1
+    patch at the source; scaling every weight leaves it unchanged."""
+    obs, src = cfg1
+    N = orc.patch_normalised(obs, src)
+    c = src.nl // 2
+    assert abs(N[c, c] - 1.0) < 1e-12
+    off = ps.Source(l0=src.l0, m0=src.m0, l_first=src.l0 + 40 * ps.ARCSEC, m_first=src.m0 - 25 * ps.ARCSEC,
+                    dl=3 * ps.ARCSEC, dm=2 * ps.ARCSEC, nl=7, nm=5)
+    at_src = ps.Source(l0=src.l0, m0=src.m0, l_first=src.l0, m_first=src.m0, dl=1.0, dm=1.0, nl=1, nm=1)
+    ref = orc.patch_brute(obs, off).real / orc.patch_brute(obs, at_src).real[0, 0]
+    assert np.max(np.abs(orc.patch_normalised(obs, off) - ref)) < 1e-12
+    obs3 = ps.Observation(**{**obs.__dict__, "W": (3.0 * obs.W).astype(np.float32)})
+    assert np.max(np.abs(orc.patch_normalised(obs3, off) - orc.patch_normalised(obs, off))) < 1e-13
+
+
 def test_brute_force_with_explicit_conjugates(cfg1):
     obs, src = cfg1
     small = ps.Source.centred(src.l0, src.m0, 9, 7 * ps.ARCSEC, nm=11)
