@@ -131,6 +131,22 @@ typedef struct psf_src {
   int64_t out_off;
 } psf_src;
 
+/* psf_patch without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same computation and kernels as psf_patch (D and
+ * prec, PSF_NORMALISE included, as there), run on a scratch array of
+ * 320 MiB that the library holds on every GPU it runs on until the process
+ * ends.  It allocates nothing and calls no allocating routine.  Fails with
+ * PSF_EWORKSPACE when the patch needs more than that scratch (its records
+ * take 40 bytes per bin: about 7 million bins at 257 x 257); use
+ * psf_patch with a workspace then.  The first call on a device looks up the
+ * scratch address of that device (make it outside graph capture).  Every
+ * call on a GPU shares that GPU's scratch: calls that overlap in time on
+ * one GPU (different streams, or host threads) race and must be ordered by
+ * the caller.  Nothing in the scratch needs to start at zero. */
+int psf_patch_noalloc(const psf_obs* obs, const psf_src* h_src, const float* D, int prec,
+                      float* P, void* stream);
+
 /* Workspace bytes needed by psf_patch and psf_patch_fullw (n_src = 1),
  * psf_patch_batched and psf_patch_backward for these sources and precision.
  * h_srcs is a host array.  Writes the size to *out (host). */

@@ -64,6 +64,8 @@ _SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
     "psf_patch": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P, _P,
                                  ctypes.c_size_t, _P]),
+    "psf_patch_noalloc": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int, _P,
+                                         _P]),
     "psf_patch_batched": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
                                          ctypes.c_int, ctypes.c_char_p, _P, _P, ctypes.c_size_t, _P]),
     "psf_patch_backward": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.c_int32, ctypes.POINTER(PsfSrc), _P,
@@ -296,6 +298,22 @@ def patch(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, wor
         D_ptr = Dr.data_ptr()
     code = _prec(prec) | (PSF_NORMALISE if normalise else 0)
     psf_patch(dobs.struct, hs, D_ptr, code, P.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    return P
+
+
+def patch_noalloc(dobs: DeviceObservation, src, prec="split_bf16", D=None, out=None, normalise: bool = False):
+    """``patch`` on the library's fixed scratch (``psf_patch_noalloc``): no
+    workspace is allocated; raises PsfError (PSF_EWORKSPACE) when the patch
+    needs more than that scratch."""
+    torch = _torch()
+    hs = make_src(src)
+    P = torch.empty((int(src.nl), int(src.nm)), dtype=torch.float32, device=dobs.device) if out is None else out
+    D_ptr = None
+    if D is not None:
+        D_ptr = (torch.view_as_real(D) if D.is_complex() else D).data_ptr()
+    code = _prec(prec) | (PSF_NORMALISE if normalise else 0)
+    _check(lib().psf_patch_noalloc(ctypes.byref(dobs.struct), ctypes.byref(hs), D_ptr, code, P.data_ptr(),
+                                   _stream_handle()))
     return P
 
 

@@ -410,3 +410,57 @@ int psf_patch(const psf_obs* obs, const psf_src* h_src, const float* D, int prec
 }
 
 }  // extern "C"
+// ====================================================================== no-allocation variant
+namespace psf {
+namespace {
+// Scratch of psf_patch_noalloc: one array per GPU, in the library's code
+// object, held until the process ends.  320 MiB holds the per-bin records
+// (40 bytes per bin), partial slabs and peak of one patch: K up to about
+// 6.5 million bins at 257 x 257, more for smaller patches.
+constexpr size_t kNoAllocScratchBytes = size_t(320) << 20;
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+// Device address of this device's copy of `scratch`, resolved once per
+// device with that device current.  In host code the array's name is only
+// a host-side stand-in: every kernel argument uses the resolved address.
+int scratch_address(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;  // per device
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(addr.size()) <= dev) addr.resize(dev + 1, nullptr);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return PSF_OK;
+}
+}  // namespace
+}  // namespace psf
+
+extern "C" int psf_patch_noalloc(const psf_obs* obs, const psf_src* h_src, const float* D, int prec, float* P,
+                                 void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_obs(obs)) != PSF_OK) return st;
+  if ((st = validate_src(h_src, 0)) != PSF_OK) return st;
+  if ((st = validate_prec(prec)) != PSF_OK) return st;
+  if (P == nullptr) return fail(PSF_EINVAL, "P is NULL");
+  const size_t need = patch_workspace(obs, plan_patch(obs, h_src, prec_base(prec), kTargetWorkgroups));
+  if (need > kNoAllocScratchBytes)
+    return fail(PSF_EWORKSPACE,
+                "psf_patch_noalloc needs %zu bytes of scratch for this observation and patch; its fixed scratch "
+                "holds %zu (use psf_patch with a workspace)",
+                need, kNoAllocScratchBytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != PSF_OK) return st;
+  // psf_patch on the library's scratch: nothing in it needs to start at zero
+  // (every partial slab, record and peak is written before it is read)
+  return psf_patch(obs, h_src, D, prec, P, ws, kNoAllocScratchBytes, stream);
+}
