@@ -51,8 +51,11 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="if > 0: only run this many headline steps of --prec (for rocprofv3) and print "
                          "nothing else")
-    ap.add_argument("--profile-workload", default="bda256", choices=["bda256", "meerkat257"],
-                    help="what --profile-steps runs: headline graph replays or single uniform-bin PSFs")
+    ap.add_argument("--profile-workload", default="bda256",
+                    choices=["bda256", "meerkat257", "adjoint129", "decorr-bda", "decorr-meerkat"],
+                    help="what --profile-steps runs: headline graph replays, single uniform-bin PSFs, the "
+                         "16-source 129x129 adjoint, or decorrelation factors of one source (headline or "
+                         "uniform-bin workload)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="if > 0: only copy a buffer of this many MiB a few times (calibrates the HBM "
                          "byte counters against a plain copy kernel) and print nothing else")
@@ -445,14 +448,27 @@ def main():
         print(f"copied {a.copy_mib} MiB 3 times", flush=True)
         return
 
-    if a.profile_steps > 0 and a.profile_workload == "meerkat257":
-        obs = ps.observation(2, seed=a.seed)
-        src = ps.sources(2, seed=a.seed)[0]
+    if a.profile_steps > 0 and a.profile_workload != "bda256":
+        cfg = 5 if a.profile_workload == "decorr-bda" else 2
+        obs = ps.observation(cfg, seed=a.seed)
+        src = ps.sources(cfg, seed=a.seed)[0]
         dobs = pk.DeviceObservation(obs)
-        for _ in range(a.profile_steps):
-            pk.patch(dobs, src, prec=a.prec, workspace=ws)
+        if a.profile_workload == "adjoint129":
+            srcs = ps.sources(3, seed=a.seed)
+            G = torch.randn(sum(s.nl * s.nm for s in srcs), dtype=torch.float32, device="cuda")
+            for _ in range(a.profile_steps):
+                pk.patch_backward(dobs, srcs, G, a.prec, workspace=ws)
+        elif a.profile_workload.startswith("decorr"):
+            # the decorrelation as the patch path runs it (factors, records and
+            # W D written per bin), here ahead of a small 65 x 65 contraction
+            small = ps.Source.centred(src.l0, src.m0, 65, src.dl)
+            for _ in range(a.profile_steps):
+                pk.patch(dobs, small, prec=a.prec, workspace=ws)
+        else:
+            for _ in range(a.profile_steps):
+                pk.patch(dobs, src, prec=a.prec, workspace=ws)
         torch.cuda.synchronize()
-        print(f"profiled {a.profile_steps} single PSFs of {a.prec}", flush=True)
+        print(f"profiled {a.profile_steps} steps of {a.profile_workload} ({a.prec})", flush=True)
         return
 
     print("generating the headline workload", file=sys.stderr, flush=True)

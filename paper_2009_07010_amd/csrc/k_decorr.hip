@@ -131,6 +131,54 @@ __device__ __forceinline__ BinSums bin_sums(const ObsView& o, const BinRef& r, d
 }
 }  // namespace
 
+// The per-bin outputs from the bin's D (and, for the adjoint, its
+// derivatives): D, the record the contraction streams (u', v' and the
+// 16-pixel steps of both axes), c = W D, and the five adjoint coefficient
+// vectors (only where the samples were summed, has_grad).
+template <bool kGrad>
+__device__ __forceinline__ void finish_bin(const ObsView& o, int64_t k, double l0, double m0, double n0, double dl,
+                                           double dm, double nu_k, double uc, double vc, double wc, float dre,
+                                           float dim, float dDl_re, float dDl_im, float dDm_re, float dDm_im,
+                                           bool has_grad, float2* __restrict__ D_out, BinRec* __restrict__ rec_out,
+                                           float2* __restrict__ c_out, float2* __restrict__ coef_out) {
+#pragma clang fp contract(off)
+  if (D_out != nullptr) D_out[k] = make_float2(dre, dim);
+  const double s = nu_k * kInvCLight;
+  const double u = uc * s, v = vc * s, w = wc * s;
+  const double up = u - w * l0 / n0, vp = v - w * m0 / n0;
+  if (rec_out != nullptr) {
+    BinRec r;
+    r.up = up;
+    r.vp = vp;
+    const cf32 sa = expi_turns(up * (16.0 * dl)), sb = expi_turns(vp * (16.0 * dm));
+    r.step_a = make_float2(sa.re, sa.im);
+    r.step_b = make_float2(sb.re, sb.im);
+    rec_out[k] = r;
+  }
+  const float W = o.W[k];
+  const float cre = W * dre, cim = W * dim;
+  if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
+  if (kGrad && coef_out != nullptr && has_grad) {
+    // 2 pi i c t = 2 pi t (-Im c, Re c) for real t.  All five vectors are
+    // scaled by kAdjointScale (a power of two, exact) so that they stay in
+    // the FP16 range of the split-FP16 contraction (|2 pi u' c| reaches a
+    // few 1e5 on km baselines at GHz); the reduction undoes the scale.
+    const double n03 = n0 * n0 * n0;
+    const double two_pi = 6.283185307179586 * kAdjointScale;
+    const float tu = static_cast<float>(two_pi * up), tv = static_cast<float>(two_pi * vp);
+    const float t2 = static_cast<float>(-two_pi * w * (1.0 - m0 * m0) / n03);
+    const float t3 = static_cast<float>(-two_pi * w * l0 * m0 / n03);
+    const float t4 = static_cast<float>(-two_pi * w * (1.0 - l0 * l0) / n03);
+    const int64_t K = o.K;
+    const float Ws = W * static_cast<float>(kAdjointScale);
+    coef_out[k] = make_float2(Ws * dDl_re - tu * -cim, Ws * dDl_im - tu * cre);
+    coef_out[K + k] = make_float2(Ws * dDm_re - tv * -cim, Ws * dDm_im - tv * cre);
+    coef_out[2 * K + k] = make_float2(t2 * -cim, t2 * cre);
+    coef_out[3 * K + k] = make_float2(t3 * -cim, t3 * cre);
+    coef_out[4 * K + k] = make_float2(t4 * -cim, t4 * cre);
+  }
+}
+
 // One thread per bin.  Writes any subset of: D, record (u', v', c = W D),
 // and the five adjoint coefficient vectors e0..e4 (coef_out, plane e at
 // coef_out + e K).  When D_in is given the samples are not read: only the
@@ -202,41 +250,92 @@ __global__ __launch_bounds__(256) void k_decorr(ObsView o, double l0, double m0,
       dDm_im = bs.gmi * sc;
     }
   }
-  if (D_out != nullptr) D_out[k] = make_float2(dre, dim);
-  const double s = nu_k * kInvCLight;
-  const double u = uc * s, v = vc * s, w = wc * s;
-  const double up = u - w * l0 / n0, vp = v - w * m0 / n0;
-  if (rec_out != nullptr) {
-    BinRec r;
-    r.up = up;
-    r.vp = vp;
-    const cf32 sa = expi_turns(up * (16.0 * dl)), sb = expi_turns(vp * (16.0 * dm));
-    r.step_a = make_float2(sa.re, sa.im);
-    r.step_b = make_float2(sb.re, sb.im);
-    rec_out[k] = r;
+  finish_bin<kGrad>(o, k, l0, m0, n0, dl, dm, nu_k, uc, vc, wc, dre, dim, dDl_re, dDl_im, dDm_re, dDm_im,
+                    D_in == nullptr, D_out, rec_out, c_out, coef_out);
+}
+
+// Few long bins: one wave per bin.  When an observation has too few bins
+// to fill the GPU with one lane each but many samples per bin (the host's
+// choice, use_wave_bins), every wave takes one bin: lane l sums the bin's
+// samples l, l + 64, ... in (time, channel) order, then the wave's partial
+// sums are combined by a fixed butterfly of lane exchanges (deterministic,
+// rounded in another order than the one-lane loop).  The per-sample phase
+// is formed exactly as there (no fused multiply-add, so that identical rows
+// still cancel exactly).  Four waves per block; source y of the launch in
+// grid row y, as for k_decorr.
+template <bool kGrad>
+__global__ __launch_bounds__(256) void k_decorr_wave(ObsView o, double l0, double m0, double dl, double dm,
+                                                     const double* __restrict__ dirs, int64_t dir_stride,
+                                                     int64_t rec_stride, float2* __restrict__ D_out,
+                                                     BinRec* __restrict__ rec_out, float2* __restrict__ c_out,
+                                                     float2* __restrict__ coef_out) {
+#pragma clang fp contract(off)
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (k >= o.K) return;  // the whole wave
+  const int lane = threadIdx.x & 63;
+  if (dirs != nullptr) {
+    l0 = dirs[blockIdx.y * dir_stride];
+    m0 = dirs[blockIdx.y * dir_stride + 1];
+    dl = dirs[blockIdx.y * dir_stride + 4];
+    dm = dirs[blockIdx.y * dir_stride + 5];
   }
-  const float W = o.W[k];
-  const float cre = W * dre, cim = W * dim;
-  if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
-  if (kGrad && coef_out != nullptr && D_in == nullptr) {
-    // 2 pi i c t = 2 pi t (-Im c, Re c) for real t.  All five vectors are
-    // scaled by kAdjointScale (a power of two, exact) so that they stay in
-    // the FP16 range of the split-FP16 contraction (|2 pi u' c| reaches a
-    // few 1e5 on km baselines at GHz); the reduction undoes the scale.
-    const double n03 = n0 * n0 * n0;
-    const double two_pi = 6.283185307179586 * kAdjointScale;
-    const float tu = static_cast<float>(two_pi * up), tv = static_cast<float>(two_pi * vp);
-    const float t2 = static_cast<float>(-two_pi * w * (1.0 - m0 * m0) / n03);
-    const float t3 = static_cast<float>(-two_pi * w * l0 * m0 / n03);
-    const float t4 = static_cast<float>(-two_pi * w * (1.0 - l0 * l0) / n03);
-    const int64_t K = o.K;
-    const float Ws = W * static_cast<float>(kAdjointScale);
-    coef_out[k] = make_float2(Ws * dDl_re - tu * -cim, Ws * dDl_im - tu * cre);
-    coef_out[K + k] = make_float2(Ws * dDm_re - tv * -cim, Ws * dDm_im - tv * cre);
-    coef_out[2 * K + k] = make_float2(t2 * -cim, t2 * cre);
-    coef_out[3 * K + k] = make_float2(t3 * -cim, t3 * cre);
-    coef_out[4 * K + k] = make_float2(t4 * -cim, t4 * cre);
+  if (rec_out != nullptr) rec_out += blockIdx.y * rec_stride;
+  if (c_out != nullptr) c_out += blockIdx.y * rec_stride;
+  const BinRef r = locate_bin(o.koff, o.tboff, o.bl_bin, o.n_bl, o.n_t, o.n_ch, k);
+  const double n0 = sqrt(1.0 - l0 * l0 - m0 * m0);
+  const double Lw = n0 - 1.0;
+  const double nu_k = bin_freq(o.freq, r.c0, r.c1);
+  const double uc = o.uvw_c[3 * r.tb + 0], vc = o.uvw_c[3 * r.tb + 1], wc = o.uvw_c[3 * r.tb + 2];
+  const double A_k = uc * l0 + vc * m0 + wc * Lw;
+  const double A_knu = A_k * nu_k;
+  const double l0_n0 = l0 / n0, m0_n0 = m0 / n0;
+  const bool win = o.win_t != nullptr || o.win_c != nullptr;
+  const int nc = r.c1 - r.c0, n = (r.t1 - r.t0) * nc;
+  const double* rows = o.uvw + 3 * (static_cast<int64_t>(r.b) * o.n_t);
+  float v[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // S re, im; G_l re, im; G_m re, im; window sum
+  for (int idx = lane; idx < n; idx += 64) {
+    const int t = r.t0 + idx / nc, c = r.c0 + idx % nc;
+    const double u = rows[3 * t], vv = rows[3 * t + 1], w = rows[3 * t + 2];
+    const double nu_c = o.freq[c];
+    const double A_t = u * l0 + vv * m0 + w * Lw;
+    const double phi = (A_t * nu_c - A_knu) * kInvCLight;
+    const cf32 e = expi_turns_hw(-phi);
+    float x = 1.f;
+    if (win) {
+      x = (o.win_t != nullptr ? o.win_t[static_cast<int64_t>(r.b) * o.n_t + t] : 1.f) *
+          (o.win_c != nullptr ? o.win_c[static_cast<int64_t>(r.b) * o.n_ch + c] : 1.f);
+      v[6] += x;
+    }
+    v[0] += x * e.re;
+    v[1] += x * e.im;
+    if constexpr (kGrad) {
+      const double du = (u * nu_c - uc * nu_k) * kInvCLight;
+      const double dv = (vv * nu_c - vc * nu_k) * kInvCLight;
+      const double dw = (w * nu_c - wc * nu_k) * kInvCLight;
+      const float gl = x * static_cast<float>(du - dw * l0_n0);
+      const float gm = x * static_cast<float>(dv - dw * m0_n0);
+      v[2] += gl * e.im;
+      v[3] -= gl * e.re;
+      v[4] += gm * e.im;
+      v[5] -= gm * e.re;
+    }
   }
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off);
+  if (lane != 0) return;
+  const float inv = win ? (v[6] != 0.f ? 1.0f / v[6] : 0.f) : 1.0f / static_cast<float>(n);
+  const float sc = 6.283185307179586f * inv;
+  finish_bin<kGrad>(o, k, l0, m0, n0, dl, dm, nu_k, uc, vc, wc, v[0] * inv, v[1] * inv, v[2] * sc, v[3] * sc,
+                    v[4] * sc, v[5] * sc, true, D_out, rec_out, c_out, coef_out);
+}
+
+// One wave per bin pays off when one lane per bin leaves the GPU mostly
+// idle: fewer bins than 512 waves' worth and at least 64 samples per bin
+// on average.
+bool use_wave_bins(const ObsView& o) {
+  const double samples = static_cast<double>(o.n_bl) * o.n_t * o.n_ch;
+  return o.K > 0 && o.K < 512 * 64 && samples >= 64.0 * static_cast<double>(o.K);
 }
 
 hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, double dm, const float2* D_in,
@@ -244,6 +343,16 @@ hipError_t launch_decorr(const ObsView& o, double l0, double m0, double dl, doub
                          const double* dir) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
+  if (D_in == nullptr && use_wave_bins(o)) {
+    const dim3 g(static_cast<unsigned>((o.K + 3) / 4));
+    if (coef_out != nullptr)
+      hipLaunchKernelGGL(k_decorr_wave<true>, g, dim3(256), 0, stream, o, l0, m0, dl, dm, dir, int64_t(0),
+                         int64_t(0), D_out, rec_out, c_out, coef_out);
+    else
+      hipLaunchKernelGGL(k_decorr_wave<false>, g, dim3(256), 0, stream, o, l0, m0, dl, dm, dir, int64_t(0),
+                         int64_t(0), D_out, rec_out, c_out, nullptr);
+    return hipGetLastError();
+  }
   if (coef_out != nullptr && D_in == nullptr)
     hipLaunchKernelGGL(k_decorr<true>, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, stream, o, l0, m0,
                        dl, dm, dir, int64_t(0), int64_t(0), D_in, D_out, rec_out, c_out, coef_out);
@@ -257,6 +366,12 @@ hipError_t launch_decorr_sources(const ObsView& o, const double* dirs, int64_t d
                                  BinRec* rec_out, float2* c_out, int64_t rec_stride, hipStream_t stream) {
   const int threads = 256;
   const int64_t blocks = (o.K + threads - 1) / threads;
+  if (use_wave_bins(o)) {
+    hipLaunchKernelGGL(k_decorr_wave<false>, dim3(static_cast<unsigned>((o.K + 3) / 4), static_cast<unsigned>(n_src)),
+                       dim3(256), 0, stream, o, 0.0, 0.0, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, rec_out,
+                       c_out, nullptr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_decorr<false>, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(n_src)), dim3(threads), 0,
                      stream, o, 0.0, 0.0, 0.0, 0.0, dirs, dir_stride, rec_stride, nullptr, nullptr, rec_out, c_out,
                      nullptr);

@@ -402,11 +402,14 @@ struct Gen {
 template <int PREC>
 __device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstride, int row, int gv, float v0,
                                            float v1) {
-  typedef __attribute__((address_space(3))) f32x2_t lds_f32x2;
+  typedef __attribute__((address_space(3))) uint64_t lds_u64;
   typedef __attribute__((address_space(3))) uint32_t lds_u32;
   if constexpr (PREC == kFP32) {
     lds_t* p = hi_plane + (gv >> 3) * gstride + row * kRowBytes + swz(row, (gv & 7) >> 1) + (gv & 1) * 8;
-    *reinterpret_cast<lds_f32x2*>(p) = f32x2_t{v0, v1};
+    // the pair as one 64-bit word, v0 in the low half (a two-float vector
+    // store here had the compiler build the pair through scratch memory)
+    *reinterpret_cast<lds_u64*>(p) = (static_cast<uint64_t>(__builtin_bit_cast(uint32_t, v1)) << 32) |
+                                     __builtin_bit_cast(uint32_t, v0);
   } else {
     lds_t* p = hi_plane + row * kRowBytes + swz(row, gv >> 2) + (gv & 3) * 4;
     uint32_t hi, lo = 0;

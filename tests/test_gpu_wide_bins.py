@@ -109,3 +109,46 @@ def test_wide_bin_batched(pk):
         err = orc.peak_normalised_error(P.double().cpu().numpy(), orc.patch_factored(obs, s))[0]
         print(f"wide bins batched {s.nl}: {err:.2e}", flush=True)
         assert err < TOL
+
+
+def _long_bins(windowed, uneven=False):
+    """Few bins of many samples (60 x 16 = 960, or per-baseline bins of 7 to
+    60 samples by 3 to 16 channels with short last bins): too few bins to
+    fill the GPU with one lane each, so the decorrelation takes one wave per
+    bin (lane-strided samples, fixed butterfly reduction)."""
+    if uneven:
+        g = np.random.default_rng(44)
+        ants = ps.layout_disc(6, 3000.0, g)
+        bins = np.stack([g.integers(7, 61, 15), g.integers(3, 17, 15)], axis=1)
+        obs = ps.make_observation(ants, 600, 1.0, ps.channel_centres(1.3e9, 1.5e9, 64), bins,
+                                  weight_rng=np.random.default_rng(45))
+    else:
+        obs = ps.tiny_random(43, n_ant=6, n_t=600, n_ch=64, nt=60, nc=16, radius_m=3000.0, dt=1.0)
+    assert obs.K < 512 * 64 and obs.n_bl * obs.n_t * obs.n_ch >= 64 * obs.K
+    return ps.tapered_windows(obs, strength=0.8) if windowed else obs
+
+
+@pytest.mark.parametrize("windowed", [False, True])
+@pytest.mark.parametrize("uneven", [False, True])
+def test_long_bins_decorr_patch_and_gradient(pk, windowed, uneven):
+    obs = _long_bins(windowed, uneven)
+    dobs = pk.DeviceObservation(obs)
+    src = ps.Source.centred(0.004, -0.003, 65, 2.0 * ps.ARCSEC)
+    D = orc.decorr(obs, src.l0, src.m0)
+    Dg = pk.decorr(dobs, src.l0, src.m0).cpu().numpy().astype(np.complex128)
+    print(f"long bins K={obs.K} uneven={uneven} windowed={windowed} D: {np.max(np.abs(Dg - D)):.2e} "
+          f"(mean |D| {np.mean(np.abs(D)):.2f})", flush=True)
+    assert np.max(np.abs(Dg - D)) < 2e-6
+    P = orc.patch_factored(obs, src, D)
+    for prec in ("fp32", "split_bf16"):
+        err = orc.peak_normalised_error(pk.patch(dobs, src, prec=prec).double().cpu().numpy(), P)[0]
+        print(f"long bins patch {prec}: {err:.2e}", flush=True)
+        assert err < TOL
+    moved = src.with_direction(src.l0 + ps.ARCSEC, src.m0 - 0.5 * ps.ARCSEC)
+    T = orc.patch_factored(obs, moved)
+    _, g_ref, _ = orc.loss_grad_analytic(obs, [src], [1.0], [T])
+    G = torch.as_tensor(2.0 * (P - T), dtype=torch.float32, device="cuda").reshape(-1)
+    got = pk.patch_backward(dobs, [src], G, "split_bf16").cpu().numpy()
+    err = np.max(np.abs(got[0] - g_ref[0])) / np.max(np.abs(g_ref[0]))
+    print(f"long bins gradient: {err:.2e}", flush=True)
+    assert err <= 1e-4
