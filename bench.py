@@ -52,10 +52,10 @@ def parse():
                     help="if > 0: only run this many headline steps of --prec (for rocprofv3) and print "
                          "nothing else")
     ap.add_argument("--profile-workload", default="bda256",
-                    choices=["bda256", "meerkat257", "adjoint129", "decorr-bda", "decorr-meerkat"],
+                    choices=["bda256", "meerkat257", "forward129", "adjoint129", "decorr-bda", "decorr-meerkat"],
                     help="what --profile-steps runs: headline graph replays, single uniform-bin PSFs, the "
-                         "16-source 129x129 adjoint, or decorrelation factors of one source (headline or "
-                         "uniform-bin workload)")
+                         "16-source 129x129 forward or adjoint, or decorrelation factors of one source "
+                         "(headline or uniform-bin workload)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="if > 0: only copy a buffer of this many MiB a few times (calibrates the HBM "
                          "byte counters against a plain copy kernel) and print nothing else")
@@ -453,7 +453,11 @@ def main():
         obs = ps.observation(cfg, seed=a.seed)
         src = ps.sources(cfg, seed=a.seed)[0]
         dobs = pk.DeviceObservation(obs)
-        if a.profile_workload == "adjoint129":
+        if a.profile_workload == "forward129":
+            srcs = ps.sources(3, seed=a.seed)
+            for _ in range(a.profile_steps):
+                pk.patch_batched(dobs, srcs, a.prec, workspace=ws)
+        elif a.profile_workload == "adjoint129":
             srcs = ps.sources(3, seed=a.seed)
             G = torch.randn(sum(s.nl * s.nm for s in srcs), dtype=torch.float32, device="cuda")
             for _ in range(a.profile_steps):

@@ -911,8 +911,14 @@ __device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, 
 // launch's sources.  Template arguments are the two tile heights and the two
 // tile widths (in blocks) of its tile family, and the form (general or
 // symmetric) of every source of the launch.
+// Waves per SIMD: two (one workgroup per compute unit) for the large tiles,
+// whose registers and LDS fill a CU; four (two workgroups) for the 5 x 5
+// block tiles of the 65-pixel family, whose per-chunk matrix work is small
+// enough that a second workgroup's waves are needed to cover the barrier and
+// LDS latency of each chunk (16 patches of 65 pixels at K = 23.2M,
+// split-BF16: 38.0 to 28.6 ms).
 template <int PREC, int I0, int I1, int J0, int J1, bool SYM>
-__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
+__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, I0 <= 5 ? 4 : 2)))
 void k_patch(BatchArgs a) {
   constexpr int L00 = TileGeom<PREC, I0, J0, SYM>::LDS, L01 = TileGeom<PREC, I0, J1, SYM>::LDS;
   constexpr int L10 = TileGeom<PREC, I1, J0, SYM>::LDS, L11 = TileGeom<PREC, I1, J1, SYM>::LDS;
@@ -1070,6 +1076,8 @@ void plan_tiles(int nbi, int nbj, TilePlan* t) {
       t->kps[r][c] = kPatchChunk;
     }
 }
+
+int tile_wgs_per_cu(const TilePlan& t) { return t.tbi[0] <= 5 ? 2 : 1; }
 
 bool sym_patch_size(int nl, int nm) {
   const int nbj = (nm + 15) / 16;

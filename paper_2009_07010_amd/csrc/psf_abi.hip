@@ -177,7 +177,9 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
 }
 
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
-  return plan_patch_items(o, s, prec, patch_work(o, s, prec) / target_wgs);
+  TilePlan t;
+  plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
+  return plan_patch_items(o, s, prec, patch_work(o, s, prec) / (target_wgs * tile_wgs_per_cu(t)));
 }
 
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {

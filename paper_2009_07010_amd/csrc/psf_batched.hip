@@ -93,15 +93,21 @@ int parse_tuning(const char* json, std::vector<Tuning>* out) {
   return PSF_OK;
 }
 
-// Work items per CU when the caller gives no table: what the tuner picks on
-// the MeerKAT-shaped data (one for the 257- and 129-pixel families, whose
-// items are large; three for the 65-pixel family), two otherwise.
+// Work items per CU when the caller gives no table: one for the 257- and
+// 129-pixel families, whose items are large; four for the 65-pixel family,
+// whose kernel runs two workgroups per CU (two items each); two otherwise.
 int default_items_per_cu(const Family& f) {
   if (f.tbi0 == 9 && (f.tbi1 == 8 || f.tbi1 == 9)) return 1;
-  if (f.tbi0 == 5 && f.tbi1 == 5 && f.tbj0 == 5) return 3;
+  if (f.tbi0 == 5 && f.tbi1 == 5 && f.tbj0 == 5) return 4;
   return kDefaultItemsPerCU;
 }
-constexpr int kMaxDefaultItemsPerCU = 3;
+
+// Persistent contraction workgroups for a launch of `items` work items of
+// this family: one per CU, two where the kernel runs two per CU.
+int64_t launch_wgs(const TilePlan& t, int64_t items) {
+  return std::min<int64_t>(items, static_cast<int64_t>(kComputeUnits) * tile_wgs_per_cu(t));
+}
+constexpr int kMaxDefaultItemsPerCU = 4;
 
 Tuning tuning_for(const std::vector<Tuning>& table, const Family& f) {
   for (const Tuning& t : table)
@@ -221,7 +227,7 @@ int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* 
       item0 += tile_plan_items(gp.plans[q].tp);
       poff += align_up(gp.plans[q].partial_elems, 64);
     }
-    const int64_t n_wg = std::min<int64_t>(gp.items, kComputeUnits);
+    const int64_t n_wg = launch_wgs(gp.plans[0].tp, gp.items);
     int rc = run_batch(prec, a, n_wg, st);
     if (rc != PSF_OK) return rc;
   }
@@ -346,7 +352,7 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
         a.K = obs->K;
         a.src[0] = src_plan(&src, plan, rec, c, partial, P, nullptr);
         a.n_items = tile_plan_items(plan.tp);
-        const int64_t n_wg = std::min<int64_t>(a.n_items, kComputeUnits);
+        const int64_t n_wg = launch_wgs(plan.tp, a.n_items);
         constexpr int kReps = 3;
         if ((e = launch_patch(prec, a, n_wg, s)) != hipSuccess) {  // warm-up
           rc = hip_fail(e, "k_patch launch");

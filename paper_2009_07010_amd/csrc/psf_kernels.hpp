@@ -119,6 +119,9 @@ void plan_tiles(int nbi, int nbj, TilePlan* tp);
 // Whether a patch of nl x nm pixels has a compiled symmetric form (nl is
 // 65, 129 or 257 and nm falls in the same tile family).
 bool sym_patch_size(int nl, int nm);
+// Contraction workgroups one compute unit runs at once for this tile plan
+// (its kernel's occupancy): 2 for the 5 x 5 block tiles, else 1.
+int tile_wgs_per_cu(const TilePlan& t);
 // Blocks of the busiest SIMD (its two contraction waves) of a tbi x tbj tile.
 int tile_max_simd_blocks(int tbi, int tbj, bool sym);
 size_t tile_plan_partial_elems(const TilePlan& tp);

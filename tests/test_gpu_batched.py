@@ -141,8 +141,10 @@ def test_autotune_table_drives_batched_launch(pk, bda_case):
     dobs = pk.DeviceObservation(obs)
     table = pk.autotune(dobs, srcs, prec="split_bf16")
     doc = json.loads(table)
-    fams = {(f["tbi0"], f["tbi1"], f["tbj0"], f["tbj1"]) for f in doc["families"]}
-    assert fams == {(5, 5, 5, 5), (9, 9, 9, 9), (9, 8, 17, 17), (8, 8, 8, 8)}
+    fams = {(f["tbi0"], f["tbi1"], f["tbj0"], f["tbj1"], f["sym"]) for f in doc["families"]}
+    # symmetric form for the 65-, 129- and 257-row patches, the general
+    # form's 8 x 8 tiles else
+    assert fams == {(5, 5, 5, 5, 1), (9, 9, 9, 9, 1), (9, 8, 17, 17, 1), (8, 8, 8, 8, 0)}
     for f in doc["families"]:
         assert 1 <= f["items_per_cu"] <= 4 and f["flush"] in (32, 64, 128) and f["ms"] > 0
     P_all = pk.patch_batched(dobs, srcs, prec="split_bf16", tuning=table)
