@@ -63,17 +63,18 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_patch_traffic_meerkat257.txt")
+TRAFFIC_FILE_BDA = os.path.join(ROOT, "profiles", "k_patch_traffic_bda256.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_07010_amd", "csrc", "k_patch.hip")
 
 
-def measured_traffic(prec):
+def measured_traffic(prec, path=TRAFFIC_FILE):
     """HBM bytes per contraction launch from the committed counter summary,
     or None when there is none for this precision or the kernel source has
     changed since the counters were taken."""
     import hashlib
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -504,7 +505,7 @@ def main():
     print("timing the headline workload", file=sys.stderr, flush=True)
     h = headline_bda(pk, torch, ps, obs5, srcs5, a.prec, a.steps, a.warmup, ws)
     rf = roofline(a.prec, h["all_terms"], h["kernel_ms_total"], h["kernel_launches"],
-                  exec_flops=executed_flops(obs5.K, srcs5, a.prec))
+                  measured_traffic(a.prec, TRAFFIC_FILE_BDA), exec_flops=executed_flops(obs5.K, srcs5, a.prec))
     line = {
         "metric": "PSF vis·pixel terms/s at ≤1e-5 rel err vs FP64; PSFs/s, split-BF16 vs FP32",
         "value": h["terms_per_s"],

@@ -262,7 +262,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
     // (two fused multiply-adds per column; over 8 columns an element stays
     // within 3e-6, under the split representation's rounding); the jump to
     // the next k-step's first column, and its predecessor, are complex
-    // products.
+    // products from the current value, so the error carries from k-step to
+    // k-step: over a row of up to 9 k-steps (288 columns) at most about
+    // 3e-5 of an element in the worst case (the smallest column steps),
+    // incoherent across visibilities (the gradients of 257-column patches
+    // with column steps of 1e-5 to 1e-4 rad stay within 3e-7).
     const cf32 s1 = expi_turns(vp * dm), s25 = expi_turns(vp * (25.0 * dm));
     const cf32 s24 = cmul(s25, conj(s1));
     const float tc = 2.0f * s1.re;
