@@ -220,7 +220,8 @@ def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     """Hogbom CLEAN with the distorted PSF at every peak on a 257 x 257 image
     of this workload: three sources placed on pixels, dirty image formed by
     the library, `cycles` minor cycles timed (each one PSF evaluation plus
-    the peak search, subtraction and one read-back)."""
+    the peak search, subtraction and one read-back), then the same cycles
+    kept on the device and replayed from a captured graph."""
     dirty = torch.zeros((grid.nl, grid.nm), dtype=torch.float32, device="cuda")
     for i, j, f in ((60, 70, 1.0), (180, 150, 0.5), (128, 230, 0.25)):
         s = grid.with_direction(grid.l_first + i * grid.dl, grid.m_first + j * grid.dm)
@@ -230,6 +231,20 @@ def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     _, comps = pk.clean_hogbom(dobs, grid, dirty, cycles, 0.1, 0.0, prec=prec, workspace=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same cycles kept on the device (no read-back), captured once and replayed
+    res = dirty.clone()
+    cc = pk.clean_hogbom_device(dobs, grid, res, cycles, 0.1, 0.0, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.clean_hogbom_device(dobs, grid, res, cycles, 0.1, 0.0, prec=prec, workspace=ws, comps=cc)
+    res.copy_(dirty)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    dt_dev = time.perf_counter() - t0
+    del g
     # the same image with Method-2 PSFs (512 x 512 spectrum: covers the image from any peak)
     S = pk.method2_spectrum(dobs, 512, grid.dl, prec=prec, workspace=ws)
     pk.clean_hogbom_method2(S, grid, dirty, 2, 20.0, 2.5e7, 1.4e9, 0.1)
@@ -239,6 +254,7 @@ def time_clean(pk, torch, ps, dobs, grid, prec, ws, cycles=20):
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t0
     return {"image": [grid.nl, grid.nm], "cycles": len(comps), "ms_per_cycle": dt / max(1, len(comps)) * 1e3,
+            "device_graph_ms_per_cycle": dt_dev / cycles * 1e3,
             "method2_psf_grid": [512, 512], "method2_cycles": len(comps2),
             "method2_ms_per_cycle": dt2 / max(1, len(comps2)) * 1e3}
 
@@ -248,7 +264,9 @@ GOLD = os.path.join(ROOT, "tests", "golden")
 
 def golden_pixels(names):
     """Stored FP64 oracle values at sampled pixels: {source index: (i, j,
-    P_ij, peak)} from the listed golden files that exist."""
+    P_ij, scale)} from the listed golden files that exist; scale is the
+    error's normaliser, max |P64| over the patch bounded below by the stored
+    pixels and the value at the source."""
     import numpy as np
     out = {}
     for n in names:
@@ -258,7 +276,9 @@ def golden_pixels(names):
         rows = np.load(f)
         for i in np.unique(rows[:, 0]).astype(int):
             sel = rows[:, 0] == i
-            out[int(i)] = (rows[sel, 1].astype(int), rows[sel, 2].astype(int), rows[sel, 3], rows[sel, 4][0])
+            # normaliser: max |P64| over the patch, bounded below by the stored pixels and the source's value
+            out[int(i)] = (rows[sel, 1].astype(int), rows[sel, 2].astype(int), rows[sel, 3],
+                           max(abs(rows[sel, 4][0]), float(np.max(np.abs(rows[sel, 3])))))
     return out
 
 
@@ -372,13 +392,13 @@ def roofline(prec, terms, kernel_ms, launches, traffic=None, kernel="k_patch", e
 def precision_workload(pk, torch, ps, ws, seed=0):
     """The precision workload (K = 23.2M, 64 sources of 257^2 at 0.1-3 deg),
     each arithmetic in one batched call: time, terms/s and the error at the
-    stored oracle pixels (four sources)."""
+    stored oracle pixels (twelve sources)."""
     import numpy as np
     obs = ps.observation(4, seed=seed)
     srcs = ps.sources(4, seed=seed)
     dobs = pk.DeviceObservation(obs)
     terms = float(obs.K) * sum(s.nl * s.nm for s in srcs)
-    gold = golden_pixels(["config4_seed0_pixels.npy"])
+    gold = golden_pixels(["config4_seed0_pixels.npy", "config4_seed0_more_pixels.npy"])
     out = {"workload": "64 antennas, 1800 x 2 s, 64 ch over 0.9-1.7 GHz, 10 s x 2 ch bins (K=23,224,320), "
                        "64 sources at 0.1-3 deg, 257x257 at 1.5 arcsec", "K": obs.K, "sources": len(srcs)}
     for prec in ("split_bf16", "split_fp16", "fp32"):

@@ -294,13 +294,31 @@ int psf_flux_backward(int32_t n_src, int64_t npix, const float* flux, const floa
  * and records the component (pixel comp_i, comp_j, amplitude gain * peak;
  * host arrays of max_iter entries; *n_comp receives the count).  Stops
  * early when |peak| < threshold; an observation without visibilities
- * (K = 0, a zero PSF) runs no cycle.  gain in (0, 1].  Synchronises the stream
- * once per cycle to read the peak: not capturable.  ws sized with
+ * (K = 0, a zero PSF) runs no cycle; a peak pixel off the sky fails with
+ * PSF_EINVAL.  gain in (0, 1].  Synchronises the stream once per cycle to
+ * read the peak: not capturable (psf_clean_hogbom_device is).  ws sized with
  * psf_clean_workspace_bytes. */
 int psf_clean_workspace_bytes(const psf_obs* obs, const psf_src* h_grid, int prec, size_t* out);
 int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t max_iter, double gain,
                      double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
                      int32_t* n_comp, void* ws, size_t ws_bytes, void* stream);
+
+/* Hogbom CLEAN with position-dependent PSFs [Algorithm 2], kept on the
+ * device so that it can be captured into a graph and replayed: as
+ * psf_clean_hogbom, but the peak is placed by a kernel (the PSF's direction
+ * goes to a source record in the workspace that the decorrelation and the
+ * contraction read when they run), the stream is never synchronised, and
+ * exactly n_iter cycles are launched.  Once |peak| falls below threshold (or
+ * is 0, or its pixel lies off the sky) cleaning stops: the remaining cycles
+ * still evaluate a PSF but subtract nothing.  comp_i, comp_j, comp_amp
+ * (n_iter entries) and *n_comp are DEVICE memory; *n_comp is written before
+ * the first cycle.  For the same inputs the residual and the components
+ * equal those of psf_clean_hogbom bit for bit (which instead fails with
+ * PSF_EINVAL at a peak off the sky).  Same workspace as
+ * psf_clean_hogbom (psf_clean_workspace_bytes); the call allocates nothing. */
+int psf_clean_hogbom_device(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t n_iter, double gain,
+                            double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
+                            int32_t* n_comp, void* ws, size_t ws_bytes, void* stream);
 
 /* Hogbom CLEAN with Method-2 PSFs [Algorithm 2 with the section 3.2
  * approximation]: as psf_clean_hogbom, but the PSF of each peak's direction

@@ -77,6 +77,9 @@ _SIGNATURES = {
     "psf_clean_hogbom": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t, _P]),
+    "psf_clean_hogbom_device": (ctypes.c_int, [ctypes.POINTER(PsfObs), ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P,
+                                               ctypes.c_size_t, _P]),
     "psf_clean_method2_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(PsfSrc),
                                                          ctypes.POINTER(ctypes.c_size_t)]),
     "psf_clean_hogbom_method2": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(PsfSrc), _P, ctypes.c_int32,
@@ -524,6 +527,35 @@ def clean_hogbom(dobs: DeviceObservation, grid, dirty, max_iter: int, gain: floa
                                   float(gain), float(threshold), _prec(prec), ci, cj, ca, ctypes.byref(n),
                                   ws.data_ptr(), ws.numel(), _stream_handle()))
     return res, [(ci[k], cj[k], ca[k]) for k in range(n.value)]
+
+
+def clean_hogbom_device(dobs: DeviceObservation, grid, residual, n_iter: int, gain: float = 0.1,
+                        threshold: float = 0.0, prec="split_bf16", workspace: Optional[Workspace] = None,
+                        comps=None):
+    """Hogbom CLEAN kept on the device (``psf_clean_hogbom_device``): exactly
+    ``n_iter`` cycles on ``residual`` (float32 [nl, nm] on the GPU, updated in
+    place), no host synchronisation, so the call can be captured into a
+    graph.  Returns (comp_i int32 [n_iter], comp_j, comp_amp float32
+    [n_iter], n_comp int32 [1]), all device tensors (``comps`` may pass them
+    in to be reused); the first n_comp entries are the components."""
+    torch = _torch()
+    h = make_src(grid)
+    need = ctypes.c_size_t(0)
+    _check(lib().psf_clean_workspace_bytes(ctypes.byref(dobs.struct), ctypes.byref(h), _prec(prec),
+                                           ctypes.byref(need)))
+    ws = (workspace or Workspace(dobs.device)).get(need.value)
+    if comps is None:
+        m = max(1, int(n_iter))
+        comps = (torch.empty(m, dtype=torch.int32, device=dobs.device),
+                 torch.empty(m, dtype=torch.int32, device=dobs.device),
+                 torch.empty(m, dtype=torch.float32, device=dobs.device),
+                 torch.empty(1, dtype=torch.int32, device=dobs.device))
+    ci, cj, ca, n = comps
+    _check(lib().psf_clean_hogbom_device(ctypes.byref(dobs.struct), ctypes.byref(h), residual.data_ptr(),
+                                         int(n_iter), float(gain), float(threshold), _prec(prec), ci.data_ptr(),
+                                         cj.data_ptr(), ca.data_ptr(), n.data_ptr(), ws.data_ptr(), ws.numel(),
+                                         _stream_handle()))
+    return comps
 
 
 def clean_hogbom_method2(S, grid, dirty, max_iter: int, dt_bin: float, dnu_bin: float, nu: float,

@@ -3,8 +3,11 @@
 // at that direction on the image grid (the same decorrelation, phase-factor
 // and contraction kernels as psf_patch), and subtracts gain * peak times the
 // PSF normalised to 1 at the peak.  The peak search and the subtraction are
-// kernels; the host reads back the peak (one synchronisation per cycle) to
-// place the next PSF.
+// kernels.  psf_clean_hogbom reads back the peak (one synchronisation per
+// cycle) to place the next PSF and to stop at the threshold;
+// psf_clean_hogbom_device places it on the device (the direction goes to a
+// device source record that the decorrelation and the contraction read at
+// run time) and runs a fixed number of cycles, so that it can be captured.
 #include <algorithm>
 #include <cmath>
 
@@ -97,6 +100,71 @@ __global__ __launch_bounds__(kMaxThreads) void k_clean_subtract_laid(float* __re
   res[idx] -= scale * P[static_cast<int64_t>(u) * N + v];
 }
 
+// The device-side state of psf_clean_hogbom_device: the source record the
+// PSF kernels read (psf_src layout: l0, m0, l_first, m_first, dl, dm, ...),
+// whether cleaning goes on, and the current cycle's amplitude.
+struct CleanState {
+  psf_src src;
+  float amp;
+  int32_t active;
+};
+
+__global__ void k_clean_init(CleanState* __restrict__ st, psf_src grid, int32_t* __restrict__ n_comp) {
+  // the grid's centre pixel: a valid direction for cycles that subtract nothing
+  grid.l0 = grid.l_first + (grid.nl / 2) * grid.dl;
+  grid.m0 = grid.m_first + (grid.nm / 2) * grid.dm;
+  st->src = grid;
+  st->amp = 0.0f;
+  st->active = 1;
+  *n_comp = 0;
+}
+
+// Cycle `it`: the peak's pixel becomes the PSF's direction and component
+// `it`, unless cleaning has stopped (|peak| below the threshold or zero, or
+// a direction off the sky), after which every cycle subtracts nothing.
+__global__ void k_clean_place(CleanState* __restrict__ st, const Peak* __restrict__ pk, int64_t n, int nm,
+                              double threshold, double gain, int it, int32_t* __restrict__ ci,
+                              int32_t* __restrict__ cj, float* __restrict__ ca, int32_t* __restrict__ n_comp) {
+  // the direction rounded as the host forms it in psf_clean_hogbom (no fused multiply-add)
+#pragma clang fp contract(off)
+  const Peak p = *pk;
+  bool go = st->active != 0 && p.idx >= 0 && p.idx < n && p.absval >= threshold && p.absval != 0.0f;
+  int i = 0, j = 0;
+  double l0 = 0.0, m0 = 0.0;
+  if (go) {
+    i = static_cast<int>(p.idx / nm);
+    j = static_cast<int>(p.idx % nm);
+    l0 = st->src.l_first + i * st->src.dl;
+    m0 = st->src.m_first + j * st->src.dm;
+    go = l0 * l0 + m0 * m0 < 1.0;
+  }
+  if (!go) {
+    st->active = 0;
+    st->amp = 0.0f;
+    return;
+  }
+  st->src.l0 = l0;
+  st->src.m0 = m0;
+  st->amp = static_cast<float>(gain) * p.val;
+  ci[it] = i;
+  cj[it] = j;
+  ca[it] = static_cast<float>(gain * p.val);
+  *n_comp = it + 1;
+}
+
+// residual -= amp * P / P[peak index] (amp = gain * peak, or 0 once
+// cleaning has stopped), as k_clean_subtract.
+__global__ __launch_bounds__(kMaxThreads) void k_clean_subtract_dev(float* __restrict__ res,
+                                                                     const float* __restrict__ P, int64_t n,
+                                                                     const Peak* __restrict__ pk,
+                                                                     const CleanState* __restrict__ st) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x;
+  if (i >= n || st->active == 0) return;
+  const float p0 = P[pk->idx];
+  const float scale = p0 != 0.0f ? st->amp / p0 : 0.0f;
+  res[i] -= scale * P[i];
+}
+
 struct M2CleanLayout {
   size_t part, peak, P, work, total;
 };
@@ -121,7 +189,7 @@ int validate_m2_clean(int32_t N, const psf_src* grid) {
 }
 
 struct CleanLayout {
-  size_t patch, P, part, peak, total;
+  size_t patch, P, part, peak, state, total;
 };
 
 CleanLayout clean_layout(const psf_obs* o, const psf_src* grid, int prec) {
@@ -131,7 +199,8 @@ CleanLayout clean_layout(const psf_obs* o, const psf_src* grid, int prec) {
   L.P = align_up(patch_workspace(o, plan), 256);
   L.part = L.P + align_up(static_cast<size_t>(grid->nl) * grid->nm * sizeof(float), 256);
   L.peak = L.part + align_up(kMaxBlocks * sizeof(Peak), 256);
-  L.total = L.peak + align_up(sizeof(Peak), 256);
+  L.state = L.peak + align_up(sizeof(Peak), 256);
+  L.total = L.state + align_up(sizeof(CleanState), 256);
   return L;
 }
 
@@ -221,6 +290,57 @@ int psf_clean_hogbom(const psf_obs* obs, const psf_src* h_grid, float* residual,
   }
   hipError_t e = hipStreamSynchronize(s);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+int psf_clean_hogbom_device(const psf_obs* obs, const psf_src* h_grid, float* residual, int32_t n_iter, double gain,
+                            double threshold, int prec, int32_t* comp_i, int32_t* comp_j, float* comp_amp,
+                            int32_t* n_comp, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_clean(obs, h_grid, prec)) != PSF_OK) return st;
+  if (residual == nullptr || n_comp == nullptr) return fail(PSF_EINVAL, "residual or n_comp is NULL");
+  if (n_iter < 0) return fail(PSF_EINVAL, "n_iter < 0");
+  if (n_iter > 0 && (comp_i == nullptr || comp_j == nullptr || comp_amp == nullptr))
+    return fail(PSF_EINVAL, "component arrays are NULL");
+  if (!(gain > 0.0 && gain <= 1.0)) return fail(PSF_EINVAL, "gain %g outside (0, 1]", gain);
+  if (!(threshold >= 0.0)) return fail(PSF_EINVAL, "threshold must be >= 0");
+  const CleanLayout L = clean_layout(obs, h_grid, prec);
+  if (ws == nullptr || ws_bytes < L.total)
+    return fail(PSF_EWORKSPACE, "psf_clean_hogbom_device needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  BinRec* rec = reinterpret_cast<BinRec*>(w);
+  float2* c = reinterpret_cast<float2*>(w + align_up(static_cast<size_t>(obs->K) * sizeof(BinRec), 256));
+  float* partial = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(c) +
+                                            align_up(static_cast<size_t>(obs->K) * sizeof(float2), 256));
+  float* P = reinterpret_cast<float*>(w + L.P);
+  Peak* part = reinterpret_cast<Peak*>(w + L.part);
+  Peak* peak = reinterpret_cast<Peak*>(w + L.peak);
+  CleanState* state = reinterpret_cast<CleanState*>(w + L.state);
+  const double* dir = reinterpret_cast<const double*>(&state->src);
+  const PatchPlan plan = plan_patch(obs, h_grid, prec, kTargetWorkgroups);
+  const int64_t n = static_cast<int64_t>(h_grid->nl) * h_grid->nm;
+  const int nb = static_cast<int>(std::min<int64_t>(kMaxBlocks, (n + kMaxThreads - 1) / kMaxThreads));
+  hipLaunchKernelGGL(k_clean_init, dim3(1), dim3(1), 0, s, state, *h_grid, n_comp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_clean_init launch");
+  if (obs->K == 0) return PSF_OK;  // no visibilities: the PSF is zero, nothing to subtract
+  for (int it = 0; it < n_iter; ++it) {
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(kMaxThreads), 0, s, residual, n, part);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kMaxThreads), 0, s, part, nb, peak);
+    hipLaunchKernelGGL(k_clean_place, dim3(1), dim3(1), 0, s, state, peak, n, h_grid->nm, threshold, gain, it,
+                       comp_i, comp_j, comp_amp, n_comp);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "peak search launch");
+    if ((e = launch_decorr(view(obs), 0.0, 0.0, h_grid->dl, h_grid->dm, nullptr, nullptr, rec, c, nullptr, s,
+                           dir)) != hipSuccess)
+      return hip_fail(e, "k_decorr launch");
+    if ((st = contract(obs, h_grid, plan, prec, rec, c, partial, P, s, dir)) != PSF_OK) return st;
+    hipLaunchKernelGGL(k_clean_subtract_dev, dim3(static_cast<unsigned>((n + kMaxThreads - 1) / kMaxThreads)),
+                       dim3(kMaxThreads), 0, s, residual, P, n, peak, state);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_clean_subtract_dev launch");
+  }
+  return PSF_OK;
 }
 
 int psf_clean_method2_workspace_bytes(int32_t N, const psf_src* h_grid, size_t* out) {

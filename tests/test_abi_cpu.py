@@ -180,6 +180,21 @@ def test_clean_argument_errors(L):
     assert need.value > 65 * 65 * 4
 
 
+def test_clean_on_device_argument_errors(L):
+    """psf_clean_hogbom_device validates like psf_clean_hogbom, on the host
+    and before any launch (its component arrays are device pointers)."""
+    o, g = fake_obs(), fake_src()
+    args = lambda res, iters, gain, thr, comp, wsb: (ctypes.byref(o), ctypes.byref(g), res, iters, gain, thr, 1,
+                                                    comp, comp, comp, FAKE, FAKE, wsb, None)
+    for bad in (args(FAKE, 4, 0.0, 0.0, FAKE, 1 << 30), args(FAKE, 4, 1.5, 0.0, FAKE, 1 << 30),
+                args(None, 4, 0.1, 0.0, FAKE, 1 << 30), args(FAKE, -1, 0.1, 0.0, FAKE, 1 << 30),
+                args(FAKE, 4, 0.1, -1.0, FAKE, 1 << 30), args(FAKE, 4, 0.1, 0.0, None, 1 << 30)):
+        st, _ = status_of(L.psf_clean_hogbom_device, *bad)
+        assert st == pk.PSF_EINVAL
+    st, msg = status_of(L.psf_clean_hogbom_device, *args(FAKE, 4, 0.1, 0.0, FAKE, 16))
+    assert st == pk.PSF_EWORKSPACE and "workspace" in msg
+
+
 def test_fullw_host_side_errors(L):
     o = fake_obs()
     n = ctypes.c_int32(0)
