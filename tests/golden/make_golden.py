@@ -193,6 +193,30 @@ def config4():
                "columns: source index, i, j, P_ij, peak 2 Re sum W D")
 
 
+CONFIG4_MORE_SOURCES = [20, 41, 53, 21, 56, 12, 34, 54]    # radii 0.2, 1.04, 2.36, 2.57, 2.94, 2.95, 2.95, 2.96 deg
+
+
+def config4_more():
+    """Workload 4: FP64 values at 20 sampled pixels of eight more of its 64
+    sources (the nearest, one at 1 deg and the farthest six, where the split
+    forms' errors are largest), with each patch's peak."""
+    obs = ps.observation(4, seed=0)
+    srcs = ps.sources(4, seed=0)
+    pix = config5_pixels([srcs[i] for i in CONFIG4_MORE_SOURCES], 20)
+    t = time.time()
+    rows = []
+    for i, ij in zip(CONFIG4_MORE_SOURCES, pix):
+        D = orc.decorr(obs, srcs[i].l0, srcs[i].m0)
+        P = orc.patch_pixels(obs, srcs[i], ij[:, 0], ij[:, 1], D)
+        peak = 2.0 * float(np.sum(obs.W.astype(np.float64) * D.real))
+        rows += [(i, a, b, v, peak) for (a, b), v in zip(ij, P)]
+        print("config4 source", i, time.time() - t, flush=True)
+    np.save(os.path.join(HERE, "config4_seed0_more_pixels.npy"), np.array(rows, dtype=np.float64))
+    _meta("config4_seed0_more", config=4, seed=0, K=obs.K, sources=CONFIG4_MORE_SOURCES, seconds=time.time() - t,
+          what="oracle.patch_pixels (FP64) at sampled pixels of eight more sources of workload 4; "
+               "columns: source index, i, j, P_ij, peak 2 Re sum W D")
+
+
 def config2_windows():
     """Workload 2 with the tapered baseline-dependent windows of
     ``psf_synth.tapered_windows`` (strength 1): sampled D and sampled pixels

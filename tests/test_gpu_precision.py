@@ -2,8 +2,9 @@
 over 0.9-1.7 GHz averaged to 10 s x 2 channels (K = 23.2M visibilities), 64
 sources at radii 0.1-3 deg with 257 x 257 patches at 1.5 arcsec, all in one
 batched call per precision.  Split-BF16, split-FP16 and FP32 contractions
-against the FP64 oracle at sampled pixels of four sources (max and RMS,
-peak-normalised, <= 1e-5), and the split forms against the FP32 one over
+against the FP64 oracle at sampled pixels of twelve sources, from the
+nearest (0.2 deg) to the six farthest (2.94-2.96 deg) (max and RMS,
+normalised by the patch's largest |P64|, <= 1e-5), and the split forms against the FP32 one over
 every pixel of all 64 PSFs (reported per PSF)."""
 import json
 import math
@@ -48,16 +49,34 @@ def runs(pk):
     return obs, srcs, out
 
 
+def _scale(rows):
+    """The error's normaliser, max |P64| over the patch, bounded below by what
+    the golden rows hold: the largest stored |P64| and |P64(source)|.  Far
+    sources of this wide band can have a small or negative P at the source
+    itself (its bins decorrelate with either sign), so that value alone is
+    not the patch's largest."""
+    return max(abs(rows[0, 4]), float(np.max(np.abs(rows[:, 3]))))
+
+
+def _gold():
+    """Stored FP64 pixels of workload 4 from every golden file there is."""
+    metas, rows = [], []
+    for tag in ("config4_seed0", "config4_seed0_more"):
+        if os.path.exists(os.path.join(GOLD, tag + "_pixels.npy")):
+            metas.append(json.load(open(os.path.join(GOLD, tag + ".json"))))
+            rows.append(np.load(os.path.join(GOLD, tag + "_pixels.npy")))
+    return metas, np.concatenate(rows)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16", "fp32"])
 def test_precision_workload_against_fp64(runs, prec):
     obs, srcs, out = runs
-    meta = json.load(open(os.path.join(GOLD, "config4_seed0.json")))
-    assert obs.K == meta["K"]
-    rows = np.load(os.path.join(GOLD, "config4_seed0_pixels.npy"))
-    for i in meta["sources"]:
+    metas, rows = _gold()
+    assert all(obs.K == m["K"] for m in metas)
+    for i in [i for m in metas for i in m["sources"]]:
         sel = rows[:, 0] == i
         ii, jj = rows[sel, 1].astype(int), rows[sel, 2].astype(int)
-        d = (out[prec][i][ii, jj] - rows[sel, 3]) / abs(rows[sel, 4][0])
+        d = (out[prec][i][ii, jj] - rows[sel, 3]) / _scale(rows[sel])
         emax, erms = np.max(np.abs(d)), math.sqrt(np.mean(d * d))
         r = math.degrees(math.hypot(srcs[i].l0, srcs[i].m0))
         print(f"workload 4 {prec} source {i} ({r:.2f} deg): max {emax:.2e} rms {erms:.2e}", flush=True)
