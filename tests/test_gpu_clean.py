@@ -150,3 +150,21 @@ def test_clean_on_device_graph_replay(pk):
         for a, b in zip(comps, eager[1:]):
             assert torch.equal(a, b), f"replay {r}: components"
         _ = torch.randn(1024, device="cuda").sum()  # unrelated eager work between replays
+
+
+def test_clean_on_device_zero_cycles_and_threshold_above_peak(pk):
+    """No cycle asked for, and a threshold above the dirty peak: the residual
+    is the dirty image and no component is recorded (the count is written
+    by the call itself, whatever the arrays held)."""
+    obs, grid, dirty = _setup([(20, 11, 0.7)], n=33)
+    dobs = pk.DeviceObservation(obs)
+    d = torch.as_tensor(dirty, dtype=torch.float32, device="cuda")
+    for n_iter, thr in ((0, 0.0), (4, float(np.max(np.abs(dirty))) * 1.01)):
+        res = d.clone()
+        comps = [torch.full((max(1, n_iter),), -3, dtype=torch.int32, device="cuda"),
+                 torch.full((max(1, n_iter),), -3, dtype=torch.int32, device="cuda"),
+                 torch.zeros(max(1, n_iter), dtype=torch.float32, device="cuda"),
+                 torch.full((1,), 99, dtype=torch.int32, device="cuda")]
+        pk.clean_hogbom_device(dobs, grid, res, n_iter, 0.2, thr, comps=comps)
+        torch.cuda.synchronize()
+        assert int(comps[3].item()) == 0 and torch.equal(res, d)

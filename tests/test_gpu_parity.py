@@ -291,8 +291,8 @@ def _empty_observation():
 
 def test_empty_observation_through_every_entry_point():
     """K = 0: the patch, the batched patches, the exact-w patch, the Method-2
-    spectrum and patches and the adjoint are all zero, and CLEAN runs no
-    cycle; the FP64 oracle's patch is zero too."""
+    spectrum and patches and the adjoint are all zero, and CLEAN (host-driven
+    and on the device) runs no cycle; the FP64 oracle's patch is zero too."""
     obs = _empty_observation()
     assert obs.K == 0
     src = ps.Source.centred(0.01, -0.02, 33, 2.0 * ps.ARCSEC)
@@ -314,6 +314,10 @@ def test_empty_observation_through_every_entry_point():
     res, comps = pk.clean_hogbom(dobs, src, dirty, 5)
     torch.cuda.synchronize()
     assert comps == [] and torch.equal(res.cpu(), dirty)
+    res = dirty.to("cuda").clone()
+    _, _, _, n_comp = pk.clean_hogbom_device(dobs, src, res, 5)
+    torch.cuda.synchronize()
+    assert int(n_comp.item()) == 0 and torch.equal(res.cpu(), dirty)
 
 
 @pytest.mark.parametrize("prec", ACCURATE)
