@@ -334,6 +334,20 @@ int psf_clean_hogbom_method2(int32_t N, const float* S, const psf_src* h_grid, f
                              int32_t* comp_i, int32_t* comp_j, float* comp_amp, int32_t* n_comp, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* Hogbom CLEAN with Method-2 PSFs [Algorithm 2 with the section 3.2
+ * approximation], kept on the device as psf_clean_hogbom_device is for
+ * exact PSFs: the peak is placed by a kernel, the Method-2 patch reads its
+ * direction from device memory, exactly n_iter cycles are launched (those
+ * past the threshold subtract nothing), no synchronisation, so the loop can
+ * be captured into a graph.  comp_i, comp_j, comp_amp (n_iter entries) and
+ * *n_comp are DEVICE memory.  For the same inputs the residual and the
+ * components equal those of psf_clean_hogbom_method2 bit for bit.  ws sized
+ * with psf_clean_method2_workspace_bytes; the call allocates nothing. */
+int psf_clean_hogbom_method2_device(int32_t N, const float* S, const psf_src* h_grid, float* residual,
+                                    int32_t n_iter, double gain, double threshold, double dt_bin, double dnu_bin,
+                                    double nu, int32_t* comp_i, int32_t* comp_j, float* comp_amp, int32_t* n_comp,
+                                    void* ws, size_t ws_bytes, void* stream);
+
 /* Times candidate launch shapes for these sources with HIP events and
  * writes a JSON tuning table (host buffer json_out, capacity json_cap).
  * Synchronises the stream: not capturable. */

@@ -86,6 +86,10 @@ _SIGNATURES = {
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_double, _P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P,
                                                 ctypes.c_size_t, _P]),
+    "psf_clean_hogbom_method2_device": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(PsfSrc), _P,
+                                                       ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P,
+                                                       _P, _P, _P, ctypes.c_size_t, _P]),
     "psf_flux_scale": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
     "psf_flux_backward": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, _P, _P]),
     "psf_timing_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -580,3 +584,33 @@ def clean_hogbom_method2(S, grid, dirty, max_iter: int, dt_bin: float, dnu_bin: 
                                           ci, cj, ca, ctypes.byref(n), ws.data_ptr(), ws.numel(),
                                           _stream_handle()))
     return res, [(ci[k], cj[k], ca[k]) for k in range(n.value)]
+
+def clean_hogbom_method2_device(S, grid, residual, n_iter: int, dt_bin: float, dnu_bin: float, nu: float,
+                                gain: float = 0.1, threshold: float = 0.0, workspace: Optional[Workspace] = None,
+                                comps=None):
+    """Hogbom CLEAN with Method-2 PSFs kept on the device
+    (``psf_clean_hogbom_method2_device``): exactly ``n_iter`` cycles on
+    ``residual`` (float32 [nl, nm] on the GPU, updated in place), no host
+    synchronisation.  Returns (comp_i, comp_j, comp_amp, n_comp) device
+    tensors as ``clean_hogbom_device`` does."""
+    torch = _torch()
+    N = int(S.shape[0])
+    h = make_src(grid)
+    need = ctypes.c_size_t(0)
+    _check(lib().psf_clean_method2_workspace_bytes(N, ctypes.byref(h), ctypes.byref(need)))
+    ws = (workspace or Workspace(S.device)).get(need.value)
+    if comps is None:
+        m = max(1, int(n_iter))
+        comps = (torch.empty(m, dtype=torch.int32, device=S.device),
+                 torch.empty(m, dtype=torch.int32, device=S.device),
+                 torch.empty(m, dtype=torch.float32, device=S.device),
+                 torch.empty(1, dtype=torch.int32, device=S.device))
+    ci, cj, ca, n = comps
+    Sr = torch.view_as_real(S) if S.is_complex() else S
+    _check(lib().psf_clean_hogbom_method2_device(N, Sr.data_ptr(), ctypes.byref(h), residual.data_ptr(),
+                                                 int(n_iter), float(gain), float(threshold), float(dt_bin),
+                                                 float(dnu_bin), float(nu), ci.data_ptr(), cj.data_ptr(),
+                                                 ca.data_ptr(), n.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                 _stream_handle()))
+    return comps
+

@@ -107,6 +107,7 @@ struct CleanState {
   psf_src src;
   float amp;
   int32_t active;
+  int32_t pi, pj;  // the current peak pixel (where a Method-2 PSF is laid)
 };
 
 __global__ void k_clean_init(CleanState* __restrict__ st, psf_src grid, int32_t* __restrict__ n_comp) {
@@ -116,6 +117,8 @@ __global__ void k_clean_init(CleanState* __restrict__ st, psf_src grid, int32_t*
   st->src = grid;
   st->amp = 0.0f;
   st->active = 1;
+  st->pi = grid.nl / 2;
+  st->pj = grid.nm / 2;
   *n_comp = 0;
 }
 
@@ -145,6 +148,8 @@ __global__ void k_clean_place(CleanState* __restrict__ st, const Peak* __restric
   }
   st->src.l0 = l0;
   st->src.m0 = m0;
+  st->pi = i;
+  st->pj = j;
   st->amp = static_cast<float>(gain) * p.val;
   ci[it] = i;
   cj[it] = j;
@@ -165,8 +170,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_clean_subtract_dev(float* __res
   res[i] -= scale * P[i];
 }
 
+// residual -= amp * P / P(centre) with the Method-2 PSF laid on the
+// current peak pixel (both from the device state), as k_clean_subtract_laid.
+__global__ __launch_bounds__(kMaxThreads) void k_clean_subtract_laid_dev(float* __restrict__ res, int nl, int nm,
+                                                                          const float* __restrict__ P, int N,
+                                                                          const CleanState* __restrict__ st) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kMaxThreads + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nl) * nm || st->active == 0) return;
+  const int a = static_cast<int>(idx / nm), b = static_cast<int>(idx - static_cast<int64_t>(a) * nm);
+  const int u = a - st->pi + N / 2, v = b - st->pj + N / 2;
+  if (u < 0 || u >= N || v < 0 || v >= N) return;
+  const float scale = st->amp / P[static_cast<int64_t>(N / 2) * N + N / 2];
+  res[idx] -= scale * P[static_cast<int64_t>(u) * N + v];
+}
+
 struct M2CleanLayout {
-  size_t part, peak, P, work, total;
+  size_t part, peak, P, work, state, total;
 };
 
 M2CleanLayout m2_clean_layout(int32_t N) {
@@ -175,7 +194,8 @@ M2CleanLayout m2_clean_layout(int32_t N) {
   L.peak = align_up(kMaxBlocks * sizeof(Peak), 256);
   L.P = L.peak + align_up(sizeof(Peak), 256);
   L.work = L.P + align_up(static_cast<size_t>(N) * N * sizeof(float), 256);
-  L.total = L.work + align_up(static_cast<size_t>(N) * N * sizeof(float2), 256);
+  L.state = L.work + align_up(static_cast<size_t>(N) * N * sizeof(float2), 256);
+  L.total = L.state + align_up(sizeof(CleanState), 256);
   return L;
 }
 
@@ -405,6 +425,54 @@ int psf_clean_hogbom_method2(int32_t N, const float* S, const psf_src* h_grid, f
   }
   hipError_t e = hipStreamSynchronize(s);
   return e == hipSuccess ? PSF_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+int psf_clean_hogbom_method2_device(int32_t N, const float* S, const psf_src* h_grid, float* residual,
+                                    int32_t n_iter, double gain, double threshold, double dt_bin, double dnu_bin,
+                                    double nu, int32_t* comp_i, int32_t* comp_j, float* comp_amp, int32_t* n_comp,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  int st;
+  if ((st = validate_m2_clean(N, h_grid)) != PSF_OK) return st;
+  if (S == nullptr || residual == nullptr || n_comp == nullptr) return fail(PSF_EINVAL, "S, residual or n_comp is NULL");
+  if (n_iter < 0) return fail(PSF_EINVAL, "n_iter < 0");
+  if (n_iter > 0 && (comp_i == nullptr || comp_j == nullptr || comp_amp == nullptr))
+    return fail(PSF_EINVAL, "component arrays are NULL");
+  if (!(gain > 0.0 && gain <= 1.0)) return fail(PSF_EINVAL, "gain %g outside (0, 1]", gain);
+  if (!(threshold >= 0.0)) return fail(PSF_EINVAL, "threshold must be >= 0");
+  if (!(dt_bin >= 0.0) || !(dnu_bin >= 0.0) || !(nu > 0.0) || !std::isfinite(dt_bin) || !std::isfinite(dnu_bin) ||
+      !std::isfinite(nu))
+    return fail(PSF_EINVAL, "bin duration, bandwidth and frequency must be finite, >= 0 (nu > 0)");
+  const M2CleanLayout L = m2_clean_layout(N);
+  if (ws == nullptr || ws_bytes < L.total)
+    return fail(PSF_EWORKSPACE, "psf_clean_hogbom_method2_device needs %zu workspace bytes, got %zu", L.total,
+                ws_bytes);
+  if ((st = check_device()) != PSF_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  Peak* part = reinterpret_cast<Peak*>(w + L.part);
+  Peak* peak = reinterpret_cast<Peak*>(w + L.peak);
+  float* P = reinterpret_cast<float*>(w + L.P);
+  float2* work = reinterpret_cast<float2*>(w + L.work);
+  CleanState* state = reinterpret_cast<CleanState*>(w + L.state);
+  const double* dir = reinterpret_cast<const double*>(&state->src);
+  const int64_t n = static_cast<int64_t>(h_grid->nl) * h_grid->nm;
+  const int nb = static_cast<int>(std::min<int64_t>(kMaxBlocks, (n + kMaxThreads - 1) / kMaxThreads));
+  hipLaunchKernelGGL(k_clean_init, dim3(1), dim3(1), 0, s, state, *h_grid, n_comp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_clean_init launch");
+  for (int it = 0; it < n_iter; ++it) {
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(kMaxThreads), 0, s, residual, n, part);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kMaxThreads), 0, s, part, nb, peak);
+    hipLaunchKernelGGL(k_clean_place, dim3(1), dim3(1), 0, s, state, peak, n, h_grid->nm, threshold, gain, it,
+                       comp_i, comp_j, comp_amp, n_comp);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "peak search launch");
+    if ((st = method2_patch_device_dir(N, h_grid->dl, S, dir, dt_bin, dnu_bin, nu, P, work, s)) != PSF_OK) return st;
+    hipLaunchKernelGGL(k_clean_subtract_laid_dev, dim3(static_cast<unsigned>((n + kMaxThreads - 1) / kMaxThreads)),
+                       dim3(kMaxThreads), 0, s, residual, h_grid->nl, h_grid->nm, P, N, state);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_clean_subtract_laid_dev launch");
+  }
+  return PSF_OK;
 }
 
 }  // extern "C"

@@ -58,6 +58,11 @@ size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
 // and coefficients c (c_k = W_k D_k for the patch itself).
 // dir (optional): the source's direction and grid in device memory
 // (psf_src layout), read at run time instead of h_src's.
+// One Method-2 patch (psf_method2_patch's arithmetic) with its direction
+// read from device memory at d_dir (l0, m0); work: N^2 complex values.
+int method2_patch_device_dir(int32_t N, double cell, const float* S, const double* d_dir, double dt_bin,
+                             double dnu_bin, double nu, float* P, float2* work, hipStream_t s);
+
 int contract(const psf_obs* obs, const psf_src* h_src, const PatchPlan& plan, int prec, const BinRec* rec,
              const float2* c, float* partial, float* P, hipStream_t s, const double* dir = nullptr,
              const double* peak = nullptr);

@@ -75,16 +75,19 @@ struct Dirs {
   double l0[kChunk], m0[kChunk];
 };
 
-// work[s][a][b] = S[a][b] D^(a' du, b' du; l0_s, m0_s)
+// work[s][a][b] = S[a][b] D^(a' du, b' du; l0_s, m0_s); the direction of
+// a one-source launch read from device memory (l0, m0 at ddir) when ddir
+// is not null.
 __global__ __launch_bounds__(256) void k_m2_dhat(const float2* __restrict__ S, float2* __restrict__ work, int N,
-                                                 double du, double dt, double frac_bw, Dirs d) {
+                                                 double du, double dt, double frac_bw, Dirs d,
+                                                 const double* __restrict__ ddir) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int64_t NN = static_cast<int64_t>(N) * N;
   if (e >= NN) return;
   const int s = blockIdx.y;
   const int a = static_cast<int>(e / N), b = static_cast<int>(e - static_cast<int64_t>(a) * N);
   const double u0 = (a < N / 2 ? a : a - N) * du, v0 = (b < N / 2 ? b : b - N) * du;
-  const double l0 = d.l0[s], m0 = d.m0[s];
+  const double l0 = ddir != nullptr ? ddir[0] : d.l0[s], m0 = ddir != nullptr ? ddir[1] : d.m0[s];
   const double hpsi = M_PI * kOmegaEarth * (-v0 * l0 + u0 * m0) * dt;  // dPsi / 2
   const double hphi = M_PI * frac_bw * sqrt(l0 * l0 + m0 * m0) * sqrt(u0 * u0 + v0 * v0);
   const double sp = hpsi == 0.0 ? 1.0 : sin(hpsi) / hpsi;
@@ -161,6 +164,26 @@ size_t patch_m2_workspace(int32_t N, int32_t n_src) {
 }
 
 }  // namespace
+
+// One Method-2 patch whose direction (l0, m0) is read from device memory
+// when the kernels run (the arguments validated by the caller; work holds
+// N^2 complex values).
+int method2_patch_device_dir(int32_t N, double cell, const float* S, const double* d_dir, double dt_bin,
+                             double dnu_bin, double nu, float* P, float2* work, hipStream_t s) {
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const unsigned nb = static_cast<unsigned>((NN + 255) / 256);
+  const double du = 1.0 / (N * cell);
+  hipLaunchKernelGGL(k_m2_dhat, dim3(nb, 1), dim3(256), 0, s, reinterpret_cast<const float2*>(S), work, N, du,
+                     dt_bin, dnu_bin / nu, Dirs{}, d_dir);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_m2_dhat launch");
+  int st;
+  if ((st = fft2(work, N, 1, 1.0f, s)) != PSF_OK) return st;
+  hipLaunchKernelGGL(k_m2_store, dim3(nb, 1), dim3(256), 0, s, work, P, N,
+                     static_cast<float>(1.0 / static_cast<double>(NN)));
+  e = hipGetLastError();
+  return e == hipSuccess ? PSF_OK : hip_fail(e, "k_m2_store launch");
+}
 
 }  // namespace psf
 
@@ -252,7 +275,7 @@ int psf_method2_patch(int32_t N, double cell, const float* S, int32_t n_src, con
       d.m0[q] = h_dirs[2 * (q0 + q) + 1];
     }
     hipLaunchKernelGGL(k_m2_dhat, dim3(nb, nq), dim3(256), 0, s, reinterpret_cast<const float2*>(S), work, N, du,
-                       dt_bin, dnu_bin / nu, d);
+                       dt_bin, dnu_bin / nu, d, static_cast<const double*>(nullptr));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_m2_dhat launch");
     if ((st = fft2(work, N, nq, 1.0f, s)) != PSF_OK) return st;

@@ -195,6 +195,19 @@ def test_clean_on_device_argument_errors(L):
     assert st == pk.PSF_EWORKSPACE and "workspace" in msg
 
 
+def test_clean_method2_on_device_argument_errors(L):
+    g = fake_src()
+    args = lambda N, res, iters, gain, thr, nu, comp, wsb: (N, FAKE, ctypes.byref(g), res, iters, gain, thr, 30.0,
+                                                           1e6, nu, comp, comp, comp, FAKE, FAKE, wsb, None)
+    for bad in (args(100, FAKE, 4, 0.1, 0.0, 1.4e9, FAKE, 1 << 30), args(64, None, 4, 0.1, 0.0, 1.4e9, FAKE, 1 << 30),
+                args(64, FAKE, -1, 0.1, 0.0, 1.4e9, FAKE, 1 << 30), args(64, FAKE, 4, 0.0, 0.0, 1.4e9, FAKE, 1 << 30),
+                args(64, FAKE, 4, 0.1, 0.0, 0.0, FAKE, 1 << 30), args(64, FAKE, 4, 0.1, 0.0, 1.4e9, None, 1 << 30)):
+        st, _ = status_of(L.psf_clean_hogbom_method2_device, *bad)
+        assert st == pk.PSF_EINVAL
+    st, msg = status_of(L.psf_clean_hogbom_method2_device, *args(64, FAKE, 4, 0.1, 0.0, 1.4e9, FAKE, 16))
+    assert st == pk.PSF_EWORKSPACE and "workspace" in msg
+
+
 def test_fullw_host_side_errors(L):
     o = fake_obs()
     n = ctypes.c_int32(0)

@@ -168,3 +168,39 @@ def test_clean_on_device_zero_cycles_and_threshold_above_peak(pk):
         pk.clean_hogbom_device(dobs, grid, res, n_iter, 0.2, thr, comps=comps)
         torch.cuda.synchronize()
         assert int(comps[3].item()) == 0 and torch.equal(res, d)
+
+
+@pytest.mark.parametrize("N", [128, 32])
+def test_clean_method2_on_device_equals_host_clean(pk, N):
+    """psf_clean_hogbom_method2_device against psf_clean_hogbom_method2 (a
+    threshold that stops it part way at N = 128; N = 32 lays a cut PSF): the same
+    components and residual bit for bit; then the device loop captured once
+    and replayed twice from the dirty image, each replay equal again."""
+    obs, grid, dirty = _setup([(10, 12, 1.0), (50, 44, 0.45), (33, 52, 0.2)])
+    dt, dnu, nu, gain, n_iter = 30.0, 1e6, 1.4e9, 0.5, 12
+    thr = 0.1 * float(np.max(np.abs(dirty)))
+    S = pk.method2_spectrum(pk.DeviceObservation(obs), N, grid.dl)
+    d = torch.as_tensor(dirty, dtype=torch.float32, device="cuda")
+    host_res, host_comps = pk.clean_hogbom_method2(S, grid, d, n_iter, dt, dnu, nu, gain=gain, threshold=thr)
+    # N = 128 stops at the threshold after 8 cycles; the cut N = 32 PSF leaves
+    # sidelobes above it, so there every cycle subtracts
+    assert 0 < len(host_comps) <= n_iter and (N != 128 or len(host_comps) < n_iter)
+    ws = pk.Workspace()
+    res = d.clone()
+    comps = pk.clean_hogbom_method2_device(S, grid, res, n_iter, dt, dnu, nu, gain=gain, threshold=thr, workspace=ws)
+    torch.cuda.synchronize()
+    k = int(comps[3].item())
+    got = [(int(a), int(b), float(c)) for a, b, c in zip(comps[0][:k].cpu(), comps[1][:k].cpu(), comps[2][:k].cpu())]
+    print(f"device method-2 CLEAN N={N}: {k} components in {n_iter} cycles", flush=True)
+    assert got == host_comps and torch.equal(res, host_res)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.clean_hogbom_method2_device(S, grid, res, n_iter, dt, dnu, nu, gain=gain, threshold=thr, workspace=ws,
+                                       comps=comps)
+    for r in range(2):
+        res.copy_(d)
+        comps[3].fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(res, host_res) and int(comps[3].item()) == k, f"replay {r}"
