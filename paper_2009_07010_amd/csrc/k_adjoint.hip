@@ -85,7 +85,7 @@ template <int PREC>
 __device__ __forceinline__ void split2(float p, float q, uint32_t& hi, uint32_t& lo) {
   if constexpr (PREC == kSplitFP16) {
     hi = pack_f16x2(p, q);
-    lo = pack_f16x2(p - f16_lo_to_f32(hi), q - f16_hi_to_f32(hi));
+    lo = f16_lo_pair(hi, p, q);
   } else {
     hi = pack_bf16x2(p, q);
     lo = pack_bf16x2(p - bf16_lo_to_f32(hi), q - bf16_hi_to_f32(hi));

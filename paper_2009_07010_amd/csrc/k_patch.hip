@@ -133,7 +133,7 @@ __device__ __forceinline__ void store_operand(lds_t* hi_plane, int lo_off, int g
     uint32_t hi, lo = 0;
     if constexpr (PREC == kSplitFP16) {
       hi = pack_f16x2(z.re, z.im);
-      lo = pack_f16x2(z.re - f16_lo_to_f32(hi), z.im - f16_hi_to_f32(hi));
+      lo = f16_lo_pair(hi, z.re, z.im);
     } else {
       hi = pack_bf16x2(z.re, z.im);
       if constexpr (PREC == kSplitBF16) lo = pack_bf16x2(z.re - bf16_lo_to_f32(hi), z.im - bf16_hi_to_f32(hi));
@@ -415,7 +415,7 @@ __device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstr
     uint32_t hi, lo = 0;
     if constexpr (PREC == kSplitFP16) {
       hi = pack_f16x2(v0, v1);
-      lo = pack_f16x2(v0 - f16_lo_to_f32(hi), v1 - f16_hi_to_f32(hi));
+      lo = f16_lo_pair(hi, v0, v1);
     } else {
       hi = pack_bf16x2(v0, v1);
       if constexpr (PREC == kSplitBF16) lo = pack_bf16x2(v0 - bf16_lo_to_f32(hi), v1 - bf16_hi_to_f32(hi));

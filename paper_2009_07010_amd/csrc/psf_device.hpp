@@ -137,5 +137,15 @@ __device__ __forceinline__ float f16_lo_to_f32(uint32_t p) {
 __device__ __forceinline__ float f16_hi_to_f32(uint32_t p) {
   return static_cast<float>(__builtin_bit_cast(f16x2_t, p)[1]);
 }
+// The lo halves of a split-FP16 pair, v - hi (exact in FP32), written as
+// fma(hi, -1, v) with the -1 held in a scalar register so that the compiler
+// keeps the multiply-add: with a half-precision source that is one
+// mixed-precision instruction per value instead of a conversion and a
+// subtraction.  Same values as the plain difference.
+__device__ __forceinline__ uint32_t f16_lo_pair(uint32_t hi, float v0, float v1) {
+  float m1 = -1.0f;
+  asm("" : "+s"(m1));
+  return pack_f16x2(__builtin_fmaf(f16_lo_to_f32(hi), m1, v0), __builtin_fmaf(f16_hi_to_f32(hi), m1, v1));
+}
 
 }  // namespace psf
