@@ -1,6 +1,6 @@
 """Throughput of the distorted-PSF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec split_bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec mixed_fp16]
 
 Headline workload: baseline-dependent averaging of a MeerKAT-shaped array
 (64 antennas, 2016 baselines, 14400 x 1 s, 64 channels over 1.3-1.5 GHz,
@@ -11,11 +11,16 @@ step = one replay of a captured HIP graph holding one psf_patch_batched
 call over 16 of the sources (decorrelation, phase factors, contraction
 and finalise of each); steps cycle through the 16 slices, so 16 steps
 cover all 256 sources.  The value is vis.pixel terms/s (K x nl x nm
-one-sided terms per PSF) over the timed steps.
+one-sided terms per PSF) over the timed steps, in the mixed FP16 arithmetic
+(rows one stochastically rounded FP16 value, columns split hi + lo: two
+matrix-core products per term product), whose error against the FP64
+oracle at the stored pixels is part of the line.
 
-Also printed, as keyed sub-entries: one PSF of the uniform-bin workload
-(K = 5.8M, 257^2) in split-BF16 and plain FP32; the precision workload
-(K = 23.2M, 64 sources of 257^2) in split-BF16, split-FP16 and FP32; the
+Also printed, as keyed sub-entries: the headline in split-BF16 (three
+products); one PSF of the uniform-bin workload (K = 5.8M, 257^2) in the
+headline arithmetic, split-BF16 and plain FP32; the precision workload
+(K = 23.2M, 64 sources of 257^2) in split-BF16, split-FP16, mixed-FP16 and
+FP32; the
 roofline of the contraction kernel from HIP events on its launch stream;
 the paper's two approximations, CLEAN, windows, exact w, the adjoint; and
 the FP64 CPU reference timed on a bounded sample of the headline workload.
@@ -29,13 +34,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "plain_bf16": 2516.6, "fp32": 157.3}
+PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "mixed_fp16": 2516.6, "plain_bf16": 2516.6,
+               "fp32": 157.3}
 # algorithmic work per useful one-sided term: 2 real multiply-adds
 # (Re c a Re b - Im c a Im b), 4 flops, whatever the arithmetic
 ALG_FLOPS_PER_TERM = 4.0
-# matrix-core products per term product: 3 for the split forms (hi hi, hi lo, lo hi)
-PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "plain_bf16": 1, "fp32": 1}
-DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "plain_bf16": "bf16", "fp32": "f32"}
+# matrix-core products per term product: 3 for the split forms (hi hi, hi lo, lo hi),
+# 2 for the mixed form (rows once, columns hi and lo; symmetric form, K >= 2^18,
+# else it runs split-FP16)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "mixed_fp16": 2, "plain_bf16": 1, "fp32": 1}
+MIXED_MIN_K = 1 << 18
+DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "mixed_fp16": "fp16", "plain_bf16": "bf16", "fp32": "f32"}
 
 
 def parse():
@@ -43,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="split_bf16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--prec", default="mixed_fp16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baselines", type=int, default=72,
@@ -62,16 +71,15 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_patch_traffic_meerkat257.txt")
-TRAFFIC_FILE_BDA = os.path.join(ROOT, "profiles", "k_patch_traffic_bda256.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_07010_amd", "csrc", "k_patch.hip")
 
 
-def measured_traffic(prec, path=TRAFFIC_FILE):
-    """HBM bytes per contraction launch from the committed counter summary,
-    or None when there is none for this precision or the kernel source has
-    changed since the counters were taken."""
+def measured_traffic(prec, workload="meerkat257"):
+    """HBM bytes per contraction launch from the committed counter summary
+    of this workload and precision, or None when there is none or the kernel
+    source has changed since the counters were taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_patch_traffic_{workload}_{prec}.txt")
     try:
         kv = {}
         with open(path) as f:
@@ -380,8 +388,12 @@ def executed_flops(K, srcs, prec):
     tot = 0.0
     for s in srcs:
         nbi, nbj = (s.nl + 15) // 16, (s.nm + 15) // 16
-        inner = 1 if (s.nl, nbj) in SYM_SIZES else 2
-        tot += float(K) * inner * (16 * nbi) * (16 * nbj) * 2.0 * PRODUCTS[prec]
+        sym = (s.nl, nbj) in SYM_SIZES
+        inner = 1 if sym else 2
+        prods = PRODUCTS[prec]
+        if prec == "mixed_fp16" and not (sym and K >= MIXED_MIN_K):
+            prods = PRODUCTS["split_fp16"]
+        tot += float(K) * inner * (16 * nbi) * (16 * nbj) * 2.0 * prods
     return tot
 
 
@@ -416,7 +428,7 @@ def precision_workload(pk, torch, ps, ws, seed=0):
     gold = golden_pixels(["config4_seed0_pixels.npy", "config4_seed0_more_pixels.npy"])
     out = {"workload": "64 antennas, 1800 x 2 s, 64 ch over 0.9-1.7 GHz, 10 s x 2 ch bins (K=23,224,320), "
                        "64 sources at 0.1-3 deg, 257x257 at 1.5 arcsec", "K": obs.K, "sources": len(srcs)}
-    for prec in ("split_bf16", "split_fp16", "fp32"):
+    for prec in ("split_bf16", "split_fp16", "mixed_fp16", "fp32"):
         P = pk.patch_batched(dobs, srcs, prec=prec, workspace=ws)
         torch.cuda.synchronize()
         pk.psf_timing_read()
@@ -540,7 +552,7 @@ def main():
     print("timing the headline workload", file=sys.stderr, flush=True)
     h = headline_bda(pk, torch, ps, obs5, srcs5, a.prec, a.steps, a.warmup, ws)
     rf = roofline(a.prec, h["all_terms"], h["kernel_ms_total"], h["kernel_launches"],
-                  measured_traffic(a.prec, TRAFFIC_FILE_BDA), exec_flops=executed_flops(obs5.K, srcs5, a.prec))
+                  measured_traffic(a.prec, "bda256"), exec_flops=executed_flops(obs5.K, srcs5, a.prec))
     line = {
         "metric": "PSF vis·pixel terms/s at ≤1e-5 rel err vs FP64; PSFs/s, split-BF16 vs FP32",
         "value": h["terms_per_s"],
@@ -566,6 +578,16 @@ def main():
         "all_256_eager_s": h["eager_all_256_s"],
         "roofline": rf,
     }
+    if a.prec != "split_bf16":
+        print("headline in split-BF16", file=sys.stderr, flush=True)
+        hb = headline_bda(pk, torch, ps, obs5, srcs5, "split_bf16", 16, 2, ws)
+        line["headline_split_bf16"] = {
+            "ms_per_step": hb["ms_per_step"], "terms_per_s": hb["terms_per_s"], "psfs_per_s": hb["psfs_per_s"],
+            "steps": 16, "warmup": 2, "max_rel_err_vs_fp64": max(hb["errors"].values()) if hb["errors"] else None,
+            "errors_at_oracle_pixels": hb["errors"],
+            "roofline": roofline("split_bf16", hb["all_terms"], hb["kernel_ms_total"], hb["kernel_launches"],
+                                 measured_traffic("split_bf16", "bda256"),
+                                 exec_flops=executed_flops(obs5.K, srcs5, "split_bf16"))}
     print("uniform-bin workload", file=sys.stderr, flush=True)
     obs = ps.observation(2, seed=a.seed)
     src = ps.sources(2, seed=a.seed)[0]
@@ -573,6 +595,7 @@ def main():
     terms = obs.K * src.nl * src.nm
     ms, kms, _ = time_prec(pk, torch, dobs, src, a.prec, a.steps, a.warmup, ws)
     ms32, kms32, _ = time_prec(pk, torch, dobs, src, "fp32", max(3, a.steps // 4), 1, ws)
+    msb, kmsb, _ = time_prec(pk, torch, dobs, src, "split_bf16", a.steps, a.warmup, ws)
     line["meerkat257"] = {
         "workload": "64 antennas (2016 baselines), 3600 x 2 s, 32 ch over 1.3-1.5 GHz, 20 s x 4 ch bins "
                     "(K=5,806,080), 1 source at 1 deg, 257x257 at 1.5 arcsec, one psf_patch call per PSF",
@@ -581,7 +604,10 @@ def main():
                              exec_flops=executed_flops(obs.K, [src], a.prec)),
         "fp32": {"ms_per_psf": ms32, "terms_per_s": terms / (ms32 * 1e-3),
                  "roofline": roofline("fp32", float(terms), kms32, 1,
-                                      exec_flops=executed_flops(obs.K, [src], "fp32"))}}
+                                      exec_flops=executed_flops(obs.K, [src], "fp32"))},
+        "split_bf16": {"ms_per_psf": msb, "terms_per_s": terms / (msb * 1e-3),
+                       "roofline": roofline("split_bf16", float(terms), kmsb, 1, measured_traffic("split_bf16"),
+                                            exec_flops=executed_flops(obs.K, [src], "split_bf16"))}}
     print("extras", file=sys.stderr, flush=True)
     line["method1"] = time_method1(pk, torch, dobs, src, a.prec, ws)
     line["clean"] = time_clean(pk, torch, ps, dobs, src, a.prec, ws)

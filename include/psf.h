@@ -75,8 +75,28 @@ typedef enum {
   PSF_FP32 = 0,        /* FP32 matrix-core products, FP32 accumulation */
   PSF_SPLIT_BF16 = 1,  /* operands split hi+lo in BF16, 3 products, FP32 acc */
   PSF_SPLIT_FP16 = 2,  /* operands split hi+lo in FP16, 3 products, FP32 acc */
-  PSF_PLAIN_BF16 = 3   /* single BF16 product: a negative control, not accurate */
+  PSF_PLAIN_BF16 = 3,  /* single BF16 product: a negative control, not accurate */
+  PSF_MIXED_FP16 = 4   /* see below: 2 products, for many bins */
 } psf_prec;
+
+/* PSF_MIXED_FP16: patches 65, 129 or 257 rows high (the symmetric form of
+ * the contraction) with K >= 2^18 bins.  The column factors c_k b_kj are
+ * split hi+lo in FP16 as in PSF_SPLIT_FP16; the row factors (cos and sin of
+ * the row phase) are one FP16 value each, rounded stochastically: two
+ * products instead of three.  A term is then off by up to 2^-11 of
+ * |c a b|, a bound that does not keep the patch error below 1e-5 of the
+ * peak by itself; the rounding is unbiased and its errors are independent
+ * across bins (a bin's random word comes from its index), so the patch
+ * error falls like 2^-12 sqrt(sum |c_k|^2) / |peak| (one standard
+ * deviation): the largest over a 257 x 257 patch about 2e-6 of the peak at
+ * 2^18 equally weighted bins with little decorrelation, and measured 5e-8 to
+ * 3.3e-6 on the tests' workloads (K = 5.8M to 265M, sources to 3 deg), the
+ * split forms' 7e-8 to 2.6e-6.  A patch of few effective bins (a few
+ * heavily weighted bins) or whose peak is small against sum |c_k| (strong
+ * decorrelation) has a larger error.  The result is deterministic: the
+ * same inputs give the same bits.  Smaller K, and patches of other
+ * heights, run as PSF_SPLIT_FP16; psf_patch_backward takes PSF_SPLIT_FP16
+ * products for it. */
 
 /* Flag OR-ed into prec for psf_patch, psf_patch_batched and
  * psf_workspace_bytes: the normalised PSF [section 4, errors taken on PSFs

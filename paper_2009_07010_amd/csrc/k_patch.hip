@@ -43,6 +43,16 @@
 // lo = round16(v - hi); the product uses hi*hi + hi*lo + lo*hi (three MFMAs)
 // with FP32 accumulation.
 //
+// Mixed form (symmetric form only): the columns c_k b_kj are split as above,
+// the rows (cos and sin) are one FP16 value each: a * (b_hi + b_lo), two
+// MFMAs.  Rounded to nearest, a row value would carry an error that
+// neighbouring visibilities share (their phases are nearly equal, and where
+// the phase is small cos rounds to 1 for all of them), which adds up
+// coherently over a baseline's bins.  The rows are instead rounded
+// stochastically (the conversion instruction's random-word operand, a
+// per-visibility Weyl sequence in the bin index): unbiased, with errors
+// independent across visibilities, which average out over many of them.
+//
 // Symmetric form.  With N = 2h + 1 rows, x_i = delta + (i - h) dl where
 // delta = (l_first + h dl) - l0 is the offset of the grid's centre row from
 // the source (0 for a centred grid), so a_ki = e_k a_k(s_i) with
@@ -102,7 +112,7 @@ struct TileArgs {
 
 template <int PREC>
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, f32x4 acc) {
-  if constexpr (PREC == kSplitFP16) {
+  if constexpr (PREC == kSplitFP16 || PREC == kMixedFP16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
                                                   acc, 0, 0, 0);
   } else {
@@ -160,17 +170,19 @@ struct TileGeom {
   static constexpr int TI = 16 * TBI, TJ = 16 * TBJ;
   static constexpr int RA = TI / 8, RB = TJ / 8;  // rows per generator thread (stride 8)
   static constexpr bool F32 = PREC == kFP32;
-  static constexpr bool TWO = PREC == kSplitBF16 || PREC == kSplitFP16;
+  // operands carried as hi + lo (A: tile rows, B: tile columns)
+  static constexpr bool TWOA = PREC == kSplitBF16 || PREC == kSplitFP16;
+  static constexpr bool TWOB = TWOA || PREC == kMixedFP16;
   static constexpr int GA = TI * kRowBytes, GB = TJ * kRowBytes;  // one group / plane
   static constexpr int APL = (F32 ? 2 : 1) * GA, BPL = (F32 ? 2 : 1) * GB;
-  static constexpr int NPL = TWO ? 2 : 1;
+  static constexpr int NPLA = TWOA ? 2 : 1, NPLB = TWOB ? 2 : 1;
   // symmetric form: C blocks of the tile, and B planes (Re d and Im d when
   // the tile holds both groups, else the one its rows read)
   static constexpr int CB = SYM ? sym_cb(TBI, TBJ) : TBI;
   static constexpr int NBP = SYM && CB > 0 && CB < TBI ? 2 : 1;
-  static constexpr int BUF = NPL * (APL + NBP * BPL);
+  static constexpr int BUF = NPLA * APL + NBP * NPLB * BPL;
   // byte offset of B's part (0 hi, 1 lo) of plane pl within a buffer
-  static constexpr int boff(int part, int pl) { return NPL * APL + (pl * NPL + part) * BPL; }
+  static constexpr int boff(int part, int pl) { return NPLA * APL + (pl * NPLB + part) * BPL; }
   // Chunk buffers.  2: the chunk being contracted and the chunk being
   // generated.  3: also the next chunk, complete one barrier early, so that
   // its first operand fragments can be read ahead of the barrier (measured
@@ -179,6 +191,7 @@ struct TileGeom {
   static constexpr int LDS = NBUF * BUF;
   static_assert(LDS <= 160 * 1024, "LDS of a workgroup exceeds 160 KiB");
   static_assert(!SYM || CB >= 0, "no symmetric form for this tile type");
+  static_assert(SYM || PREC != kMixedFP16, "the mixed form exists for the symmetric form only");
 };
 
 // Sub-tile of one contraction wave: m x n blocks at block (i0, j0) of the
@@ -297,7 +310,7 @@ struct Gen {
   using G = TileGeom<PREC, TBI, TBJ>;
   static constexpr int R = IS_A ? TBI : TBJ;  // rows per thread
   static constexpr int GSTRIDE = IS_A ? G::GA : G::GB;
-  static constexpr int GOFF = IS_A ? 0 : G::NPL * G::APL;
+  static constexpr int GOFF = IS_A ? 0 : G::NPLA * G::APL;
   static constexpr int GLO = IS_A ? G::APL : G::BPL;
   static constexpr int P = 1;  // chunks of records held ahead
 
@@ -425,6 +438,21 @@ __device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstr
   }
 }
 
+// Mixed form: two row values of visibilities 2 gv and 2 gv + 1 (random
+// words r0, r1) as one FP16 value each, rounded stochastically: the
+// conversion adds the top bits of the random word below the kept ones and
+// truncates, so each value rounds up with probability equal to its
+// fractional position between its two FP16 neighbours.
+__device__ __forceinline__ void store_pair_sr(lds_t* plane, int row, int gv, float v0, float v1, uint32_t r0,
+                                              uint32_t r1) {
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
+  f16x2_t h = {};
+  h = __builtin_amdgcn_cvt_sr_f16_f32(h, v0, r0, false);
+  h = __builtin_amdgcn_cvt_sr_f16_f32(h, v1, r1, true);
+  *reinterpret_cast<lds_u32*>(plane + row * kRowBytes + swz(row, gv >> 2) + (gv & 3) * 4) =
+      __builtin_bit_cast(uint32_t, h);
+}
+
 // Phase-factor generation of the symmetric form (see the file comment).
 // Thread (gv, rc) owns visibilities 2 gv and 2 gv + 1 of each 32-visibility
 // chunk and row (column) class rc.  A (waves 0-3): unit n of its sequence
@@ -440,6 +468,9 @@ __device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstr
 template <int PREC, int TBI, int TBJ, bool IS_A>
 struct GenSym {
   using G = TileGeom<PREC, TBI, TBJ, true>;
+  // how this side's values are stored (the mixed form's rows: store_pair_sr)
+  static constexpr int OP = PREC == kMixedFP16 ? kSplitFP16 : PREC;
+  static constexpr bool SR = IS_A && PREC == kMixedFP16;
   static constexpr int CB = G::CB;
   static constexpr bool HC = CB > 0, HS = CB < TBI;
   static constexpr int N0 = IS_A && !HC ? 1 : 0;
@@ -463,6 +494,8 @@ struct GenSym {
   cf32 rst[P][2];
   cf32 rcc[P][2];
   bool rok[P][2];
+  uint32_t rrw[P][2];  // mixed form (A): the bins' random words
+  uint32_t rw[2];
   cf32 z[2], zp[2];
   float tc[2];
   lds_t* plane;
@@ -479,8 +512,12 @@ struct GenSym {
     kb = kb_;
     ke = ke_;
   }
-  __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok) const {
+  __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok,
+                                        uint32_t& rwd) const {
     const int64_t kg = kb + n * kPatchChunkSym + 2 * gv + e;
+    // the random word of bin kg: kg times the golden ratio mod 2^32, whose
+    // top bits (the ones the conversion uses) are equidistributed in kg
+    if (SR) rwd = static_cast<uint32_t>(kg) * 0x9E3779B1u;
     ok = kg < ke;
     const int64_t kc = ok ? kg : ke - 1;
     const BinRec* r = recs + kc;
@@ -497,11 +534,12 @@ struct GenSym {
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) fetch(j, e, rf[j][e], ru[j][e], rst[j][e], rcc[j][e], rok[j][e]);
+      for (int e = 0; e < 2; ++e) fetch(j, e, rf[j][e], ru[j][e], rst[j][e], rcc[j][e], rok[j][e], rrw[j][e]);
   }
   __device__ __forceinline__ void begin(lds_t* smem, int buf) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
+      if (SR) rw[e] = rrw[0][e];
       z[e] = expi_turns_hw(rf[0][e] * pos0);
       const cf32 zs = rst[0][e];
       if (!IS_A) {
@@ -539,19 +577,24 @@ struct GenSym {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       if (q < q0 || q >= q1) continue;
-      if constexpr (IS_A) {
+      if constexpr (SR) {
         const int n = N0 + q;
-        if (HC && n < CB) store_pair<PREC>(plane, LO, GSTRIDE, 16 * n + rc, gv, z[0].re, z[1].re);
+        if (HC && n < CB) store_pair_sr(plane, 16 * n + rc, gv, z[0].re, z[1].re, rw[0], rw[1]);
         if (HS && n >= 1 && CB + n - 1 < TBI)
-          store_pair<PREC>(plane, LO, GSTRIDE, 16 * (CB + n - 1) + rc, gv, z[0].im, z[1].im);
+          store_pair_sr(plane, 16 * (CB + n - 1) + rc, gv, z[0].im, z[1].im, rw[0], rw[1]);
+      } else if constexpr (IS_A) {
+        const int n = N0 + q;
+        if (HC && n < CB) store_pair<OP>(plane, LO, GSTRIDE, 16 * n + rc, gv, z[0].re, z[1].re);
+        if (HS && n >= 1 && CB + n - 1 < TBI)
+          store_pair<OP>(plane, LO, GSTRIDE, 16 * (CB + n - 1) + rc, gv, z[0].im, z[1].im);
       } else {
         if constexpr (BOTH) {
-          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
-          store_pair<PREC>(plane + G::NPL * G::BPL, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
+          store_pair<OP>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
+          store_pair<OP>(plane + G::NPLB * G::BPL, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
         } else if constexpr (ONLY_IM) {
-          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
+          store_pair<OP>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].im, z[1].im);
         } else {
-          store_pair<PREC>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
+          store_pair<OP>(plane, LO, GSTRIDE, 16 * q + rc, gv, z[0].re, z[1].re);
         }
       }
       if (q + 1 < R) step();
@@ -567,9 +610,11 @@ struct GenSym {
         rst[j][e] = rst[j + 1][e];
         rcc[j][e] = rcc[j + 1][e];
         rok[j][e] = rok[j + 1][e];
+        rrw[j][e] = rrw[j + 1][e];
       }
 #pragma unroll
-    for (int e = 0; e < 2; ++e) fetch(n, e, rf[P - 1][e], ru[P - 1][e], rst[P - 1][e], rcc[P - 1][e], rok[P - 1][e]);
+    for (int e = 0; e < 2; ++e)
+      fetch(n, e, rf[P - 1][e], ru[P - 1][e], rst[P - 1][e], rcc[P - 1][e], rok[P - 1][e], rrw[P - 1][e]);
   }
 };
 
@@ -594,8 +639,9 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
   // symmetric form's S rows read Im d when the tile holds both groups)
   constexpr int CH = SYM ? kPatchChunkSym : kChunk;
   constexpr int BP = G::NBP == 2 && WI0 >= G::CB ? 1 : 0;
-  // generation rows spread over the contraction steps of a chunk
-  constexpr int NSTEP = G::F32 ? 2 * N : N + M;
+  // generation rows spread over the contraction steps of a chunk (the
+  // mixed form has no second pass)
+  constexpr int NSTEP = G::F32 ? 2 * N : PREC == kMixedFP16 ? N : N + M;
   typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
   typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
   const int lane = threadIdx.x & 63;
@@ -660,7 +706,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
 #pragma unroll
       for (int r = 0; r < M; ++r) pah[r] = ldA(Ah, 0, r);
       pbh = ldB(Ah, 0, 0);
-      if constexpr (G::TWO) pbl = ldB(Ah, 1, 0);
+      if constexpr (G::TWOB) pbl = ldB(Ah, 1, 0);
     }
   };
   int cur = 0;  // buffer of chunk n
@@ -705,8 +751,8 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
         }
       } else {
         // pass 1: A_hi x (B_hi, B_lo), keeping every B_hi fragment;
-        // pass 2: A_lo x B_hi.  Loads run one column (pass 1) or one row
-        // (pass 2) ahead of their MFMAs.
+        // pass 2 (split forms): A_lo x B_hi.  Loads run one column (pass 1)
+        // or one row (pass 2) ahead of their MFMAs.
         bf16x8 bh[N];
         bf16x8 nbh = pbh, nbl = pbl;
 #pragma unroll
@@ -715,17 +761,17 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
           const bf16x8 bl = nbl;
           if (c + 1 < N) {
             nbh = ldB(Ah, 0, c + 1);
-            if constexpr (G::TWO) nbl = ldB(Ah, 1, c + 1);
+            if constexpr (G::TWOB) nbl = ldB(Ah, 1, c + 1);
           }
 #pragma unroll
           for (int r = 0; r < M; ++r) {
             if (!on(r, c)) continue;
             acc[r][c] = mfma16<PREC>(pah[r], bh[c], acc[r][c]);
-            if constexpr (G::TWO) acc[r][c] = mfma16<PREC>(pah[r], bl, acc[r][c]);
+            if constexpr (G::TWOB) acc[r][c] = mfma16<PREC>(pah[r], bl, acc[r][c]);
           }
           gen_step();
         }
-        if constexpr (G::TWO) {
+        if constexpr (G::TWOA) {
           bf16x8 nal = ldA(Ah, 1, 0);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
@@ -736,7 +782,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
               if (on(r, c)) acc[r][c] = mfma16<PREC>(al, bh[c], acc[r][c]);
             gen_step();
           }
-        } else {
+        } else if constexpr (PREC != kMixedFP16) {
 #pragma unroll
           for (int r = 0; r < M; ++r) gen_step();
         }
@@ -1098,15 +1144,19 @@ static hipError_t launch_family(const BatchArgs& a, dim3 grid, hipStream_t strea
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  if (t.tbi[0] == 9 && t.tbi[1] == 8)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17, false>), grid, dim3(512), 0, stream, a);
-  else if (t.tbi[0] == 9)
-    hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9, false>), grid, dim3(512), 0, stream, a);
-  else if (t.tbi[0] == 5)
-    hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5, false>), grid, dim3(512), 0, stream, a);
-  else
-    hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8, false>), grid, dim3(512), 0, stream, a);
-  return hipGetLastError();
+  if constexpr (PREC == kMixedFP16) {
+    return hipErrorInvalidValue;  // symmetric form only
+  } else {
+    if (t.tbi[0] == 9 && t.tbi[1] == 8)
+      hipLaunchKernelGGL((k_patch<PREC, 9, 8, 17, 17, false>), grid, dim3(512), 0, stream, a);
+    else if (t.tbi[0] == 9)
+      hipLaunchKernelGGL((k_patch<PREC, 9, 9, 9, 9, false>), grid, dim3(512), 0, stream, a);
+    else if (t.tbi[0] == 5)
+      hipLaunchKernelGGL((k_patch<PREC, 5, 5, 5, 5, false>), grid, dim3(512), 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_patch<PREC, 8, 8, 8, 8, false>), grid, dim3(512), 0, stream, a);
+    return hipGetLastError();
+  }
 }
 
 hipError_t launch_patch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t stream) {
@@ -1122,6 +1172,7 @@ hipError_t launch_patch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t 
     case kSplitBF16: return launch_family<kSplitBF16>(a, grid, stream);
     case kSplitFP16: return launch_family<kSplitFP16>(a, grid, stream);
     case kPlainBF16: return launch_family<kPlainBF16>(a, grid, stream);
+    case kMixedFP16: return launch_family<kMixedFP16>(a, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

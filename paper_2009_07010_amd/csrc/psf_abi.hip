@@ -86,7 +86,7 @@ int validate_src(const psf_src* s, int idx) {
 
 int validate_prec(int prec) {
   const int base = prec_base(prec);
-  if (base < PSF_FP32 || base > PSF_PLAIN_BF16) return fail(PSF_EINVAL, "unknown precision %d", prec);
+  if (base < PSF_FP32 || base > PSF_MIXED_FP16) return fail(PSF_EINVAL, "unknown precision %d", prec);
   return PSF_OK;
 }
 
@@ -126,8 +126,13 @@ bool sym_source(const psf_src* s) { return sym_patch_size(s->nl, s->nm); }
 // chunk for seeds and records, twice that in the symmetric form, 4.7 cycles
 // each).  Measured kernels behave closer to the sum of the two than to their
 // maximum.
-static void chunk_costs(const TilePlan& t, int prec, bool sym, double cost[2][2]) {
-  const double mfma_per_block = prec == PSF_FP32 ? 256.0 : prec == PSF_PLAIN_BF16 ? 16.0 : 48.0;
+static void chunk_costs(const TilePlan& t, int prec, bool sym, int64_t K, double cost[2][2]) {
+  // (the mixed form runs two products where it runs at all, see
+  // contraction_prec: plans of its split-FP16 routes are split-FP16 plans)
+  const double mfma_per_block = prec == PSF_FP32                                        ? 256.0
+                                : prec == PSF_PLAIN_BF16                                ? 16.0
+                                : prec == PSF_MIXED_FP16 && sym && K >= kMixedMinK ? 32.0
+                                                                                        : 48.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c], sym);
@@ -146,7 +151,7 @@ double patch_work(const psf_obs* o, const psf_src* s, int prec) {
   plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
   const bool sym = sym_source(s);
   double cost[2][2];
-  chunk_costs(t, prec, sym, cost);
+  chunk_costs(t, prec, sym, o->K, cost);
   const int cnt_i[2] = {t.ti_a, t.ti_b}, cnt_j[2] = {t.tj_a, t.tj_b};
   const double chunks = static_cast<double>(chunk_count(o, sym));
   double work = 0.0;
@@ -163,7 +168,7 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
   const int64_t chunks = chunk_count(o, p.sym);
   const int64_t ch = p.sym ? kPatchChunkSym : kPatchChunk;
   double cost[2][2];
-  chunk_costs(t, prec, p.sym, cost);
+  chunk_costs(t, prec, p.sym, o->K, cost);
   // k-slices per tile so that every work item costs about item_work
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
@@ -215,14 +220,22 @@ SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec,
   return p;
 }
 
+int contraction_prec(int prec, const BatchArgs& a) {
+  int kp = prec_base(prec);
+  // a few bins: split-BF16's per-term error (3 2^-16 of a term) is not
+  // averaged away, so FP32 products run instead (same plan, negligible cost)
+  if (kp == PSF_SPLIT_BF16 && a.K < kSmallK) kp = PSF_FP32;
+  // the mixed form needs many bins, and exists for the symmetric form only
+  // (every source of a launch shares the form)
+  if (kp == PSF_MIXED_FP16 && (a.K < kMixedMinK || !a.src[0].sym)) kp = PSF_SPLIT_FP16;
+  return kp;
+}
+
 int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
   hipEvent_t ev0;
   hipError_t e;
   if ((e = timed_launch_begin(s, &ev0)) != hipSuccess) return hip_fail(e, "timing event");
-  // a few bins: split-BF16's per-term error (3 2^-16 of a term) is not
-  // averaged away, so FP32 products run instead (same plan, negligible cost)
-  int kp = prec_base(prec);
-  if (kp == PSF_SPLIT_BF16 && a.K < kSmallK) kp = PSF_FP32;
+  const int kp = contraction_prec(prec, a);
   e = launch_patch(kp, a, n_wg, s);
   if (e != hipSuccess) return hip_fail(e, "k_patch launch");
   if ((e = timed_launch_end(s, ev0)) != hipSuccess) return hip_fail(e, "timing event");

@@ -80,7 +80,12 @@ struct BackwardLayout {
   size_t rec, coef, partial, pe, adj, total;
 };
 
+// Gradients take split-FP16 products where the forward runs the mixed form
+// (whose statistical rounding bound is stated for patches only).
+int backward_prec(int prec) { return prec == PSF_MIXED_FP16 ? PSF_SPLIT_FP16 : prec; }
+
 BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
+  prec = backward_prec(prec);
   size_t partial = 0, pix = 0;
   for (int s = 0; s < n_src; ++s) {
     partial = std::max(partial, plan_patch(o, &h_srcs[s], prec, kTargetWorkgroups).partial_elems);
@@ -182,6 +187,7 @@ extern "C" int psf_patch_backward(const psf_obs* obs, int32_t n_src, const psf_s
   if ((st = validate_obs(obs)) != PSF_OK) return st;
   if ((st = validate_prec(prec)) != PSF_OK) return st;
   if ((st = reject_normalise(prec, "psf_patch_backward")) != PSF_OK) return st;
+  prec = backward_prec(prec);
   if (n_src < 1 || h_srcs == nullptr) return fail(PSF_EINVAL, "need n_src >= 1 sources");
   for (int s = 0; s < n_src; ++s)
     if ((st = validate_src(&h_srcs[s], s)) != PSF_OK) return st;

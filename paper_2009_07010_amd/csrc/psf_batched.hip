@@ -354,7 +354,8 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
         a.n_items = tile_plan_items(plan.tp);
         const int64_t n_wg = launch_wgs(plan.tp, a.n_items);
         constexpr int kReps = 3;
-        if ((e = launch_patch(prec, a, n_wg, s)) != hipSuccess) {  // warm-up
+        const int kp = contraction_prec(prec, a);
+        if ((e = launch_patch(kp, a, n_wg, s)) != hipSuccess) {  // warm-up
           rc = hip_fail(e, "k_patch launch");
           break;
         }
@@ -362,7 +363,7 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
           rc = hip_fail(e, "hipEventRecord");
           break;
         }
-        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_patch(prec, a, n_wg, s);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_patch(kp, a, n_wg, s);
         if (e != hipSuccess) {
           rc = hip_fail(e, "k_patch launch");
           break;

@@ -17,6 +17,10 @@ constexpr int kTargetWorkgroups = 256;
 constexpr int kFlushChunks = 128;
 // Below this many bins the split-BF16 contraction runs as FP32.
 constexpr int64_t kSmallK = 256;
+// Below this many bins (and for patches without a symmetric form) the mixed
+// FP16 contraction runs as split-FP16: its rows' single-FP16 rounding
+// averages out only over many visibilities.
+constexpr int64_t kMixedMinK = int64_t(1) << 18;
 
 struct PatchPlan {
   TilePlan tp;
@@ -53,6 +57,9 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
 // Tile plan with about target_wgs work items.
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs);
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
+// The precision a contraction launch of `a` runs in for the caller's prec
+// (small K and non-symmetric patches change it, see kSmallK, kMixedMinK).
+int contraction_prec(int prec, const BatchArgs& a);
 
 // The contraction and finalise of one patch from per-bin records (u', v')
 // and coefficients c (c_k = W_k D_k for the patch itself).
