@@ -1,6 +1,6 @@
 """Throughput of the distorted-PSF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec mixed_fp16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec sr_fp16]
 
 Headline workload: baseline-dependent averaging of a MeerKAT-shaped array
 (64 antennas, 2016 baselines, 14400 x 1 s, 64 channels over 1.3-1.5 GHz,
@@ -11,16 +11,17 @@ step = one replay of a captured HIP graph holding one psf_patch_batched
 call over 16 of the sources (decorrelation, phase factors, contraction
 and finalise of each); steps cycle through the 16 slices, so 16 steps
 cover all 256 sources.  The value is vis.pixel terms/s (K x nl x nm
-one-sided terms per PSF) over the timed steps, in the mixed FP16 arithmetic
-(rows one stochastically rounded FP16 value, columns split hi + lo: two
-matrix-core products per term product), whose error against the FP64
+one-sided terms per PSF) over the timed steps, in the stochastic FP16
+arithmetic (rows and columns one stochastically rounded FP16 value each:
+one matrix-core product per term product), whose error against the FP64
 oracle at the stored pixels is part of the line.
 
 Also printed, as keyed sub-entries: the headline in split-BF16 (three
 products); one PSF of the uniform-bin workload (K = 5.8M, 257^2) in the
 headline arithmetic, split-BF16 and plain FP32; the precision workload
-(K = 23.2M, 64 sources of 257^2) in split-BF16, split-FP16, mixed-FP16 and
-FP32; the
+(K = 23.2M, 64 sources of 257^2) in split-BF16, split-FP16, mixed-FP16
+(rows stochastically rounded, columns split: two products), stochastic-FP16
+and FP32; the
 roofline of the contraction kernel from HIP events on its launch stream;
 the paper's two approximations, CLEAN, windows, exact w, the adjoint; and
 the FP64 CPU reference timed on a bounded sample of the headline workload.
@@ -34,17 +35,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "mixed_fp16": 2516.6, "plain_bf16": 2516.6,
-               "fp32": 157.3}
+PEAK_TFLOPS = {"split_bf16": 2516.6, "split_fp16": 2516.6, "mixed_fp16": 2516.6, "sr_fp16": 2516.6,
+               "plain_bf16": 2516.6, "fp32": 157.3}
 # algorithmic work per useful one-sided term: 2 real multiply-adds
 # (Re c a Re b - Im c a Im b), 4 flops, whatever the arithmetic
 ALG_FLOPS_PER_TERM = 4.0
 # matrix-core products per term product: 3 for the split forms (hi hi, hi lo, lo hi),
-# 2 for the mixed form (rows once, columns hi and lo; symmetric form, K >= 2^18,
-# else it runs split-FP16)
-PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "mixed_fp16": 2, "plain_bf16": 1, "fp32": 1}
+# 2 for the mixed form (rows once, columns hi and lo), 1 for the stochastic form
+# (the last two for the symmetric form and K >= 2^18, else they run split-FP16)
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3, "mixed_fp16": 2, "sr_fp16": 1, "plain_bf16": 1, "fp32": 1}
 MIXED_MIN_K = 1 << 18
-DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "mixed_fp16": "fp16", "plain_bf16": "bf16", "fp32": "f32"}
+DTYPE = {"split_bf16": "bf16", "split_fp16": "fp16", "mixed_fp16": "fp16", "sr_fp16": "fp16", "plain_bf16": "bf16",
+         "fp32": "f32"}
 
 
 def parse():
@@ -52,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="mixed_fp16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--prec", default="sr_fp16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baselines", type=int, default=72,
@@ -391,7 +393,7 @@ def executed_flops(K, srcs, prec):
         sym = (s.nl, nbj) in SYM_SIZES
         inner = 1 if sym else 2
         prods = PRODUCTS[prec]
-        if prec == "mixed_fp16" and not (sym and K >= MIXED_MIN_K):
+        if prec in ("mixed_fp16", "sr_fp16") and not (sym and K >= MIXED_MIN_K):
             prods = PRODUCTS["split_fp16"]
         tot += float(K) * inner * (16 * nbi) * (16 * nbj) * 2.0 * prods
     return tot
@@ -428,7 +430,7 @@ def precision_workload(pk, torch, ps, ws, seed=0):
     gold = golden_pixels(["config4_seed0_pixels.npy", "config4_seed0_more_pixels.npy"])
     out = {"workload": "64 antennas, 1800 x 2 s, 64 ch over 0.9-1.7 GHz, 10 s x 2 ch bins (K=23,224,320), "
                        "64 sources at 0.1-3 deg, 257x257 at 1.5 arcsec", "K": obs.K, "sources": len(srcs)}
-    for prec in ("split_bf16", "split_fp16", "mixed_fp16", "fp32"):
+    for prec in ("split_bf16", "split_fp16", "mixed_fp16", "sr_fp16", "fp32"):
         P = pk.patch_batched(dobs, srcs, prec=prec, workspace=ws)
         torch.cuda.synchronize()
         pk.psf_timing_read()

@@ -76,7 +76,8 @@ typedef enum {
   PSF_SPLIT_BF16 = 1,  /* operands split hi+lo in BF16, 3 products, FP32 acc */
   PSF_SPLIT_FP16 = 2,  /* operands split hi+lo in FP16, 3 products, FP32 acc */
   PSF_PLAIN_BF16 = 3,  /* single BF16 product: a negative control, not accurate */
-  PSF_MIXED_FP16 = 4   /* see below: 2 products, for many bins */
+  PSF_MIXED_FP16 = 4,  /* see below: 2 products, for many bins */
+  PSF_SR_FP16 = 5      /* see below: 1 product, for many bins */
 } psf_prec;
 
 /* PSF_MIXED_FP16: patches 65, 129 or 257 rows high (the symmetric form of
@@ -96,7 +97,17 @@ typedef enum {
  * decorrelation) has a larger error.  The result is deterministic: the
  * same inputs give the same bits.  Smaller K, and patches of other
  * heights, run as PSF_SPLIT_FP16; psf_patch_backward takes PSF_SPLIT_FP16
- * products for it. */
+ * products for it.
+ *
+ * PSF_SR_FP16: as PSF_MIXED_FP16, and the column factors too are one
+ * stochastically rounded FP16 value (their own random word per bin, so that
+ * a term's two roundings are independent): one product per term product.
+ * The same statistical bound with about 1.4 times the spread (two roundings
+ * per term instead of one): measured 7e-8 to 6.3e-6 of the peak on the
+ * tests' workloads (the largest on the precision workload's 2.96 deg
+ * source, against a normaliser that is a lower bound of the patch's peak),
+ * 6.7e-7 over every pixel of the uniform-bin 257 x 257 PSF.  Same
+ * conditions and fallbacks as PSF_MIXED_FP16. */
 
 /* Flag OR-ed into prec for psf_patch, psf_patch_batched and
  * psf_workspace_bytes: the normalised PSF [section 4, errors taken on PSFs

@@ -20,10 +20,10 @@ from typing import Optional, Sequence
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsfdecorr.so")
 
-PSF_FP32, PSF_SPLIT_BF16, PSF_SPLIT_FP16, PSF_PLAIN_BF16, PSF_MIXED_FP16 = 0, 1, 2, 3, 4
+PSF_FP32, PSF_SPLIT_BF16, PSF_SPLIT_FP16, PSF_PLAIN_BF16, PSF_MIXED_FP16, PSF_SR_FP16 = 0, 1, 2, 3, 4, 5
 PSF_NORMALISE = 0x100
 PRECISIONS = {"fp32": PSF_FP32, "split_bf16": PSF_SPLIT_BF16, "split_fp16": PSF_SPLIT_FP16, "mixed_fp16": PSF_MIXED_FP16,
-              "plain_bf16": PSF_PLAIN_BF16}
+              "sr_fp16": PSF_SR_FP16, "plain_bf16": PSF_PLAIN_BF16}
 PSF_OK, PSF_EINVAL, PSF_EWORKSPACE, PSF_EDEVICE, PSF_EUNSUPPORTED = 0, -1, -2, -3, -4
 
 

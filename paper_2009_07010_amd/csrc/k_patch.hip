@@ -52,6 +52,10 @@
 // stochastically (the conversion instruction's random-word operand, a
 // per-visibility Weyl sequence in the bin index): unbiased, with errors
 // independent across visibilities, which average out over many of them.
+// Stochastic form (symmetric form only): the columns too are one
+// stochastically rounded FP16 value (their own per-visibility random word,
+// a hash of the bin index, so that a term's two roundings are independent):
+// a * b, one MFMA.
 //
 // Symmetric form.  With N = 2h + 1 rows, x_i = delta + (i - h) dl where
 // delta = (l_first + h dl) - l0 is the offset of the grid's centre row from
@@ -112,7 +116,7 @@ struct TileArgs {
 
 template <int PREC>
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, f32x4 acc) {
-  if constexpr (PREC == kSplitFP16 || PREC == kMixedFP16) {
+  if constexpr (PREC == kSplitFP16 || PREC == kMixedFP16 || PREC == kSRFP16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
                                                   acc, 0, 0, 0);
   } else {
@@ -191,7 +195,8 @@ struct TileGeom {
   static constexpr int LDS = NBUF * BUF;
   static_assert(LDS <= 160 * 1024, "LDS of a workgroup exceeds 160 KiB");
   static_assert(!SYM || CB >= 0, "no symmetric form for this tile type");
-  static_assert(SYM || PREC != kMixedFP16, "the mixed form exists for the symmetric form only");
+  static_assert(SYM || (PREC != kMixedFP16 && PREC != kSRFP16),
+                "the mixed and stochastic forms exist for the symmetric form only");
 };
 
 // Sub-tile of one contraction wave: m x n blocks at block (i0, j0) of the
@@ -468,9 +473,11 @@ __device__ __forceinline__ void store_pair_sr(lds_t* plane, int row, int gv, flo
 template <int PREC, int TBI, int TBJ, bool IS_A>
 struct GenSym {
   using G = TileGeom<PREC, TBI, TBJ, true>;
-  // how this side's values are stored (the mixed form's rows: store_pair_sr)
+  // how this side's values are stored: stochastically rounded (store_pair_sr)
+  // for the rows of the mixed form and both sides of the stochastic form,
+  // else split or FP32 (store_pair<OP>)
   static constexpr int OP = PREC == kMixedFP16 ? kSplitFP16 : PREC;
-  static constexpr bool SR = IS_A && PREC == kMixedFP16;
+  static constexpr bool SR = (IS_A && PREC == kMixedFP16) || PREC == kSRFP16;
   static constexpr int CB = G::CB;
   static constexpr bool HC = CB > 0, HS = CB < TBI;
   static constexpr int N0 = IS_A && !HC ? 1 : 0;
@@ -494,7 +501,7 @@ struct GenSym {
   cf32 rst[P][2];
   cf32 rcc[P][2];
   bool rok[P][2];
-  uint32_t rrw[P][2];  // mixed form (A): the bins' random words
+  uint32_t rrw[P][2];  // stochastic rounding: the bins' random words
   uint32_t rw[2];
   cf32 z[2], zp[2];
   float tc[2];
@@ -515,9 +522,23 @@ struct GenSym {
   __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok,
                                         uint32_t& rwd) const {
     const int64_t kg = kb + n * kPatchChunkSym + 2 * gv + e;
-    // the random word of bin kg: kg times the golden ratio mod 2^32, whose
-    // top bits (the ones the conversion uses) are equidistributed in kg
-    if (SR) rwd = static_cast<uint32_t>(kg) * 0x9E3779B1u;
+    // the random word of bin kg: for the rows kg times the golden ratio
+    // mod 2^32, whose top bits (the ones the conversion uses) are
+    // equidistributed in kg; for the columns a 32-bit mixing hash of kg
+    // (multiply-xorshift finaliser), independent of the rows' word
+    if (SR) {
+      if (IS_A) {
+        rwd = static_cast<uint32_t>(kg) * 0x9E3779B1u;
+      } else {
+        uint32_t h = static_cast<uint32_t>(kg);
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        rwd = h;
+      }
+    }
     ok = kg < ke;
     const int64_t kc = ok ? kg : ke - 1;
     const BinRec* r = recs + kc;
@@ -577,7 +598,16 @@ struct GenSym {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       if (q < q0 || q >= q1) continue;
-      if constexpr (SR) {
+      if constexpr (SR && !IS_A) {
+        if constexpr (BOTH) {
+          store_pair_sr(plane, 16 * q + rc, gv, z[0].re, z[1].re, rw[0], rw[1]);
+          store_pair_sr(plane + G::NPLB * G::BPL, 16 * q + rc, gv, z[0].im, z[1].im, rw[0], rw[1]);
+        } else if constexpr (ONLY_IM) {
+          store_pair_sr(plane, 16 * q + rc, gv, z[0].im, z[1].im, rw[0], rw[1]);
+        } else {
+          store_pair_sr(plane, 16 * q + rc, gv, z[0].re, z[1].re, rw[0], rw[1]);
+        }
+      } else if constexpr (SR) {
         const int n = N0 + q;
         if (HC && n < CB) store_pair_sr(plane, 16 * n + rc, gv, z[0].re, z[1].re, rw[0], rw[1]);
         if (HS && n >= 1 && CB + n - 1 < TBI)
@@ -640,8 +670,8 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
   constexpr int CH = SYM ? kPatchChunkSym : kChunk;
   constexpr int BP = G::NBP == 2 && WI0 >= G::CB ? 1 : 0;
   // generation rows spread over the contraction steps of a chunk (the
-  // mixed form has no second pass)
-  constexpr int NSTEP = G::F32 ? 2 * N : PREC == kMixedFP16 ? N : N + M;
+  // mixed and stochastic forms have no second pass)
+  constexpr int NSTEP = G::F32 ? 2 * N : PREC == kMixedFP16 || PREC == kSRFP16 ? N : N + M;
   typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
   typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
   const int lane = threadIdx.x & 63;
@@ -782,7 +812,7 @@ __device__ __forceinline__ void wave_item(const TileArgs& a, lds_t* smem, int bi
               if (on(r, c)) acc[r][c] = mfma16<PREC>(al, bh[c], acc[r][c]);
             gen_step();
           }
-        } else if constexpr (PREC != kMixedFP16) {
+        } else if constexpr (PREC != kMixedFP16 && PREC != kSRFP16) {
 #pragma unroll
           for (int r = 0; r < M; ++r) gen_step();
         }
@@ -1144,7 +1174,7 @@ static hipError_t launch_family(const BatchArgs& a, dim3 grid, hipStream_t strea
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  if constexpr (PREC == kMixedFP16) {
+  if constexpr (PREC == kMixedFP16 || PREC == kSRFP16) {
     return hipErrorInvalidValue;  // symmetric form only
   } else {
     if (t.tbi[0] == 9 && t.tbi[1] == 8)
@@ -1173,6 +1203,7 @@ hipError_t launch_patch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t 
     case kSplitFP16: return launch_family<kSplitFP16>(a, grid, stream);
     case kPlainBF16: return launch_family<kPlainBF16>(a, grid, stream);
     case kMixedFP16: return launch_family<kMixedFP16>(a, grid, stream);
+    case kSRFP16: return launch_family<kSRFP16>(a, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

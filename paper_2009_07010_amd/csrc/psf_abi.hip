@@ -86,7 +86,7 @@ int validate_src(const psf_src* s, int idx) {
 
 int validate_prec(int prec) {
   const int base = prec_base(prec);
-  if (base < PSF_FP32 || base > PSF_MIXED_FP16) return fail(PSF_EINVAL, "unknown precision %d", prec);
+  if (base < PSF_FP32 || base > PSF_SR_FP16) return fail(PSF_EINVAL, "unknown precision %d", prec);
   return PSF_OK;
 }
 
@@ -127,12 +127,15 @@ bool sym_source(const psf_src* s) { return sym_patch_size(s->nl, s->nm); }
 // each).  Measured kernels behave closer to the sum of the two than to their
 // maximum.
 static void chunk_costs(const TilePlan& t, int prec, bool sym, int64_t K, double cost[2][2]) {
-  // (the mixed form runs two products where it runs at all, see
-  // contraction_prec: plans of its split-FP16 routes are split-FP16 plans)
-  const double mfma_per_block = prec == PSF_FP32                                        ? 256.0
-                                : prec == PSF_PLAIN_BF16                                ? 16.0
-                                : prec == PSF_MIXED_FP16 && sym && K >= kMixedMinK ? 32.0
-                                                                                        : 48.0;
+  // (the mixed and stochastic forms run two and one products where they run
+  // at all, see contraction_prec: plans of their split-FP16 routes are
+  // split-FP16 plans)
+  const bool many = sym && K >= kMixedMinK;
+  const double mfma_per_block = prec == PSF_FP32                     ? 256.0
+                                : prec == PSF_PLAIN_BF16             ? 16.0
+                                : prec == PSF_MIXED_FP16 && many ? 32.0
+                                : prec == PSF_SR_FP16 && many    ? 16.0
+                                                                     : 48.0;
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) {
       const double mf = mfma_per_block * tile_max_simd_blocks(t.tbi[r], t.tbj[c], sym);
@@ -225,9 +228,9 @@ int contraction_prec(int prec, const BatchArgs& a) {
   // a few bins: split-BF16's per-term error (3 2^-16 of a term) is not
   // averaged away, so FP32 products run instead (same plan, negligible cost)
   if (kp == PSF_SPLIT_BF16 && a.K < kSmallK) kp = PSF_FP32;
-  // the mixed form needs many bins, and exists for the symmetric form only
-  // (every source of a launch shares the form)
-  if (kp == PSF_MIXED_FP16 && (a.K < kMixedMinK || !a.src[0].sym)) kp = PSF_SPLIT_FP16;
+  // the mixed and stochastic forms need many bins, and exist for the
+  // symmetric form only (every source of a launch shares the form)
+  if ((kp == PSF_MIXED_FP16 || kp == PSF_SR_FP16) && (a.K < kMixedMinK || !a.src[0].sym)) kp = PSF_SPLIT_FP16;
   return kp;
 }
 

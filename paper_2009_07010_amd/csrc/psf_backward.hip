@@ -80,9 +80,10 @@ struct BackwardLayout {
   size_t rec, coef, partial, pe, adj, total;
 };
 
-// Gradients take split-FP16 products where the forward runs the mixed form
-// (whose statistical rounding bound is stated for patches only).
-int backward_prec(int prec) { return prec == PSF_MIXED_FP16 ? PSF_SPLIT_FP16 : prec; }
+// Gradients take split-FP16 products where the forward runs the mixed or
+// stochastic form (whose statistical rounding bound is stated for patches
+// only).
+int backward_prec(int prec) { return prec == PSF_MIXED_FP16 || prec == PSF_SR_FP16 ? PSF_SPLIT_FP16 : prec; }
 
 BackwardLayout backward_layout(const psf_obs* o, int n_src, const psf_src* h_srcs, int prec) {
   prec = backward_prec(prec);

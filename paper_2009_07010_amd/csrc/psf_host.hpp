@@ -18,8 +18,8 @@ constexpr int kFlushChunks = 128;
 // Below this many bins the split-BF16 contraction runs as FP32.
 constexpr int64_t kSmallK = 256;
 // Below this many bins (and for patches without a symmetric form) the mixed
-// FP16 contraction runs as split-FP16: its rows' single-FP16 rounding
-// averages out only over many visibilities.
+// and stochastic FP16 contractions run as split-FP16: their single-FP16
+// roundings average out only over many visibilities.
 constexpr int64_t kMixedMinK = int64_t(1) << 18;
 
 struct PatchPlan {

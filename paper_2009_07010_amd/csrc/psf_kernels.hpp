@@ -32,8 +32,9 @@ struct BinRec {
 
 // kMixedFP16: symmetric form only; the row operand (cos and sin) is one FP16
 // value, rounded stochastically, the column operand is split hi + lo in
-// FP16 (two products).
-enum Prec : int { kFP32 = 0, kSplitBF16 = 1, kSplitFP16 = 2, kPlainBF16 = 3, kMixedFP16 = 4 };
+// FP16 (two products).  kSRFP16: symmetric form only; both operands one
+// stochastically rounded FP16 value each (one product).
+enum Prec : int { kFP32 = 0, kSplitBF16 = 1, kSplitFP16 = 2, kPlainBF16 = 3, kMixedFP16 = 4, kSRFP16 = 5 };
 
 // Tiling of one patch.  Row tiles come in two heights (ti_a tiles of tbi[0]
 // blocks, then ti_b tiles of tbi[1]), column tiles in two widths (tj_a of

@@ -97,17 +97,19 @@ def test_bad_precision_and_null_output(L):
     assert st == pk.PSF_EINVAL
 
 
-def test_mixed_precision_accepted_and_next_value_rejected(L):
-    # PSF_MIXED_FP16 passes validation; the next value is unknown
+def test_mixed_and_stochastic_precisions_accepted_and_next_value_rejected(L):
+    # PSF_MIXED_FP16 and PSF_SR_FP16 pass validation; the next value is unknown
     o = fake_obs()
     srcs = (pk.PsfSrc * 1)(fake_src())
-    need = ctypes.c_size_t(0)
-    assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, pk.PSF_MIXED_FP16, ctypes.byref(need)) == 0
-    assert need.value > 12 * 40
+    for p in (pk.PSF_MIXED_FP16, pk.PSF_SR_FP16):
+        need = ctypes.c_size_t(0)
+        assert L.psf_workspace_bytes(ctypes.byref(o), 1, srcs, p, ctypes.byref(need)) == 0
+        assert need.value > 12 * 40
     out = ctypes.c_size_t(0)
-    st, msg = status_of(L.psf_workspace_bytes, ctypes.byref(o), 1, srcs, pk.PSF_MIXED_FP16 + 1, ctypes.byref(out))
+    st, msg = status_of(L.psf_workspace_bytes, ctypes.byref(o), 1, srcs, pk.PSF_SR_FP16 + 1, ctypes.byref(out))
     assert st == pk.PSF_EINVAL and "precision" in msg
     assert pk.PRECISIONS["mixed_fp16"] == pk.PSF_MIXED_FP16 == 4
+    assert pk.PRECISIONS["sr_fp16"] == pk.PSF_SR_FP16 == 5
 
 
 def test_workspace_too_small(L):

@@ -170,7 +170,7 @@ def config5():
     return ps.observation(5, seed=0)
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "mixed_fp16", "fp32"])
+@pytest.mark.parametrize("prec", ["split_bf16", "mixed_fp16", "sr_fp16", "fp32"])
 def test_batched_config5_sampled_pixels(pk, config5, prec):
     """Workload 5 at full size (baseline-dependent averaging, K ~ 2.65e8):
     the golden sources (one per patch size) batched with 9 more, compared

@@ -1,6 +1,8 @@
-"""The mixed FP16 contraction (PSF_MIXED_FP16): the rows (cos and sin) as one
-FP16 value each, rounded stochastically, the columns split hi + lo, two
-products; it runs where the patch has the symmetric form and K >= 2^18.
+"""The FP16 contractions with stochastic rounding: the mixed form
+(PSF_MIXED_FP16: the rows, cos and sin, as one stochastically rounded FP16
+value each, the columns split hi + lo, two products) and the stochastic form
+(PSF_SR_FP16: the columns too one stochastically rounded FP16 value, one
+product); both run where the patch has the symmetric form and K >= 2^18.
 
 Here, on a medium observation (30 antennas, 800 x 2 s, 64 channels over
 1.3-1.5 GHz in 8 s x 2 channel bins, K = 2.78M): parity with the FP64
@@ -23,6 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
 CELL = 1.5 * ps.ARCSEC
+FORMS = ["mixed_fp16", "sr_fp16"]
 
 
 @pytest.fixture(scope="module")
@@ -77,45 +80,46 @@ def refs(medium):
     return out
 
 
-def test_mixed_against_oracle(pk, medium, refs):
+def test_against_oracle(pk, medium, refs):
     obs, dobs = medium
     for src, ii, jj, ref, scale in refs:
-        P = {p: pk.patch(dobs, src, prec=p).double().cpu().numpy() for p in ("mixed_fp16", "split_fp16")}
+        P = {p: pk.patch(dobs, src, prec=p).double().cpu().numpy() for p in FORMS + ["split_fp16"]}
         err = {p: float(np.max(np.abs(v[ii, jj] - ref))) / scale for p, v in P.items()}
         r = np.degrees(np.hypot(src.l0, src.m0))
-        print(f"{src.nl}^2 at {r:.1f} deg: mixed {err['mixed_fp16']:.2e} split-fp16 {err['split_fp16']:.2e}",
-              flush=True)
-        assert err["mixed_fp16"] <= TOL and err["split_fp16"] <= TOL
-        # the mixed form ran (its products differ from the split form's)
-        assert np.any(P["mixed_fp16"] != P["split_fp16"])
+        print(f"{src.nl}^2 at {r:.1f} deg: " + " ".join(f"{p} {e:.2e}" for p, e in err.items()), flush=True)
+        assert max(err.values()) <= TOL
+        # the mixed and stochastic forms ran (their products differ from the split form's)
+        assert np.any(P["mixed_fp16"] != P["split_fp16"]) and np.any(P["sr_fp16"] != P["mixed_fp16"])
 
 
-def test_mixed_repeatable_and_batched(pk, medium, refs):
+@pytest.mark.parametrize("prec", FORMS)
+def test_repeatable_and_batched(pk, medium, refs, prec):
     obs, dobs = medium
     srcs = [s for s, *_ in refs]
-    a = pk.patch(dobs, srcs[0], prec="mixed_fp16")
-    b = pk.patch(dobs, srcs[0], prec="mixed_fp16")
+    a = pk.patch(dobs, srcs[0], prec=prec)
+    b = pk.patch(dobs, srcs[0], prec=prec)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
-    parts = pk.split_patches(pk.patch_batched(dobs, srcs, prec="mixed_fp16"), srcs)
+    parts = pk.split_patches(pk.patch_batched(dobs, srcs, prec=prec), srcs)
     for (src, ii, jj, ref, scale), Pb in zip(refs, parts):
         Pb = Pb.double().cpu().numpy()
-        Ps = pk.patch(dobs, src, prec="mixed_fp16").double().cpu().numpy()
+        Ps = pk.patch(dobs, src, prec=prec).double().cpu().numpy()
         # the same rounded operands (a bin's random word is its index), other
         # k-slices: the two differ by FP32 accumulation order only, which for
         # the strongly decorrelated source (sums of terms 6 times the patch's
         # peak) reaches 2e-6 of the peak over the whole patch
         d = float(np.max(np.abs(Pb - Ps))) / scale
         e = float(np.max(np.abs(Pb[ii, jj] - ref))) / scale
-        print(f"batched {src.nl}^2: vs single {d:.2e}, vs FP64 {e:.2e}", flush=True)
+        print(f"{prec} batched {src.nl}^2: vs single {d:.2e}, vs FP64 {e:.2e}", flush=True)
         assert d <= TOL / 2 and e <= TOL
 
 
-def test_routes_to_split_fp16(pk, medium):
+@pytest.mark.parametrize("prec", FORMS)
+def test_routes_to_split_fp16(pk, medium, prec):
     obs, dobs = medium
     # a patch size without a symmetric form, K >= 2^18
     src = _source(1.0, 0.4, 100, nm=90)
-    a = pk.patch(dobs, src, prec="mixed_fp16")
+    a = pk.patch(dobs, src, prec=prec)
     b = pk.patch(dobs, src, prec="split_fp16")
     torch.cuda.synchronize()
     assert torch.equal(a, b)
@@ -124,7 +128,7 @@ def test_routes_to_split_fp16(pk, medium):
     assert small.K < 1 << 18
     ds = pk.DeviceObservation(small)
     src = _source(0.8, 1.0, 129)
-    a = pk.patch(ds, src, prec="mixed_fp16")
+    a = pk.patch(ds, src, prec=prec)
     b = pk.patch(ds, src, prec="split_fp16")
     torch.cuda.synchronize()
     assert torch.equal(a, b)
@@ -132,12 +136,13 @@ def test_routes_to_split_fp16(pk, medium):
     assert orc.peak_normalised_error(a.double().cpu().numpy(), ref)[0] <= TOL
 
 
-def test_backward_takes_split_fp16(pk, medium):
+@pytest.mark.parametrize("prec", FORMS)
+def test_backward_takes_split_fp16(pk, medium, prec):
     obs, dobs = medium
     srcs = [_source(1.0, 2.1, 129), _source(2.5, 5.2, 65)]
     g = torch.Generator(device="cpu").manual_seed(5)
     G = torch.randn(sum(s.nl * s.nm for s in srcs), generator=g, dtype=torch.float32)
-    a = pk.patch_backward(dobs, srcs, G, "mixed_fp16")
+    a = pk.patch_backward(dobs, srcs, G, prec)
     b = pk.patch_backward(dobs, srcs, G, "split_fp16")
     torch.cuda.synchronize()
     assert torch.equal(a, b)

@@ -237,7 +237,7 @@ def cfg2():
     return obs, pk.DeviceObservation(obs), src, np.load(path)
 
 
-@pytest.mark.parametrize("prec", ACCURATE + ["mixed_fp16"])
+@pytest.mark.parametrize("prec", ACCURATE + ["mixed_fp16", "sr_fp16"])
 def test_config2_full_patch(cfg2, prec):
     obs, dobs, src, P = cfg2
     Pg = gpu_patch(dobs, src, prec)

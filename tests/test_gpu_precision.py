@@ -1,12 +1,12 @@
 """The precision workload: 64 ants (2016 baselines), 1 h at 2 s, 64 channels
 over 0.9-1.7 GHz averaged to 10 s x 2 channels (K = 23.2M visibilities), 64
 sources at radii 0.1-3 deg with 257 x 257 patches at 1.5 arcsec, all in one
-batched call per precision.  Split-BF16, split-FP16, mixed-FP16 and FP32
-contractions against the FP64 oracle at sampled pixels of twelve sources,
+batched call per precision.  Split-BF16, split-FP16, mixed-FP16,
+stochastic-FP16 and FP32 contractions against the FP64 oracle at sampled pixels of twelve sources,
 from the nearest (0.2 deg) to the six farthest (2.94-2.96 deg) (max and
-RMS, normalised by the patch's largest |P64|, <= 1e-5), and the split and
-mixed forms against the FP32 one over every pixel of all 64 PSFs (reported
-per PSF)."""
+RMS, normalised by the patch's largest |P64|, <= 1e-5), and the split,
+mixed and stochastic forms against the FP32 one over every pixel of all 64
+PSFs (reported per PSF)."""
 import json
 import math
 import os
@@ -42,7 +42,7 @@ def runs(pk):
     srcs = ps.sources(4, seed=0)
     dobs = pk.DeviceObservation(obs)
     out = {}
-    for prec in ("fp32", "split_bf16", "split_fp16", "mixed_fp16"):
+    for prec in ("fp32", "split_bf16", "split_fp16", "mixed_fp16", "sr_fp16"):
         P = pk.patch_batched(dobs, srcs, prec=prec)
         torch.cuda.synchronize()
         out[prec] = [p.double().cpu().numpy() for p in pk.split_patches(P, srcs)]
@@ -69,7 +69,7 @@ def _gold():
     return metas, np.concatenate(rows)
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16", "mixed_fp16", "fp32"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16", "mixed_fp16", "sr_fp16", "fp32"])
 def test_precision_workload_against_fp64(runs, prec):
     obs, srcs, out = runs
     metas, rows = _gold()
@@ -87,12 +87,12 @@ def test_precision_workload_against_fp64(runs, prec):
 def test_precision_split_forms_against_fp32_every_pixel(runs):
     _, srcs, out = runs
     worst = 0.0
-    print("src  r(deg)  bf16 max   bf16 rms   fp16 max   fp16 rms   mixed max  mixed rms", flush=True)
+    print("src  r(deg)  bf16 max   bf16 rms   fp16 max   fp16 rms   mixed max  mixed rms  sr max     sr rms", flush=True)
     for i, s in enumerate(srcs):
         ref = out["fp32"][i]
         peak = np.max(np.abs(ref))
         line = f"{i:3d}  {math.degrees(math.hypot(s.l0, s.m0)):5.2f}"
-        for prec in ("split_bf16", "split_fp16", "mixed_fp16"):
+        for prec in ("split_bf16", "split_fp16", "mixed_fp16", "sr_fp16"):
             d = (out[prec][i] - ref) / peak
             emax = float(np.max(np.abs(d)))
             worst = max(worst, emax)
