@@ -992,9 +992,14 @@ __device__ __forceinline__ void role_loop(const BatchArgs& a, karg_plan* plans, 
 // block tiles of the 65-pixel family, whose per-chunk matrix work is small
 // enough that a second workgroup's waves are needed to cover the barrier and
 // LDS latency of each chunk (16 patches of 65 pixels at K = 23.2M,
-// split-BF16: 38.0 to 28.6 ms).
+// split-BF16: 38.0 to 28.6 ms), and four for every tile of the stochastic
+// form, whose one product per block leaves each chunk mostly latency
+// (single 257 x 257 patch at K = 5.8M: 1.58 to 1.27 ms, though the
+// compiler keeps 128 registers by spilling some of the item-loop state;
+// 16 patches of 129: 11.8 to 8.7 ms).
 template <int PREC, int I0, int I1, int J0, int J1, bool SYM>
-__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, I0 <= 5 ? 4 : 2)))
+__global__ __attribute__((amdgpu_flat_work_group_size(512, 512),
+                          amdgpu_waves_per_eu(PREC == kSRFP16 ? 4 : 2, I0 <= 5 || PREC == kSRFP16 ? 4 : 2)))
 void k_patch(BatchArgs a) {
   constexpr int L00 = TileGeom<PREC, I0, J0, SYM>::LDS, L01 = TileGeom<PREC, I0, J1, SYM>::LDS;
   constexpr int L10 = TileGeom<PREC, I1, J0, SYM>::LDS, L11 = TileGeom<PREC, I1, J1, SYM>::LDS;
@@ -1153,7 +1158,7 @@ void plan_tiles(int nbi, int nbj, TilePlan* t) {
     }
 }
 
-int tile_wgs_per_cu(const TilePlan& t) { return t.tbi[0] <= 5 ? 2 : 1; }
+int tile_wgs_per_cu(const TilePlan& t, int prec) { return t.tbi[0] <= 5 || prec == kSRFP16 ? 2 : 1; }
 
 bool sym_patch_size(int nl, int nm) {
   const int nbj = (nm + 15) / 16;

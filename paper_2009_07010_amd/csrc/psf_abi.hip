@@ -187,7 +187,8 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs) {
   TilePlan t;
   plan_tiles((s->nl + 15) / 16, (s->nm + 15) / 16, &t);
-  return plan_patch_items(o, s, prec, patch_work(o, s, prec) / (target_wgs * tile_wgs_per_cu(t)));
+  const int wgs = tile_wgs_per_cu(t, launch_prec(prec, o->K, sym_source(s)));
+  return plan_patch_items(o, s, prec, patch_work(o, s, prec) / (target_wgs * wgs));
 }
 
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p) {
@@ -223,16 +224,19 @@ SrcPlan src_plan(const psf_src* h_src, const PatchPlan& plan, const BinRec* rec,
   return p;
 }
 
-int contraction_prec(int prec, const BatchArgs& a) {
+int launch_prec(int prec, int64_t K, bool sym) {
   int kp = prec_base(prec);
   // a few bins: split-BF16's per-term error (3 2^-16 of a term) is not
   // averaged away, so FP32 products run instead (same plan, negligible cost)
-  if (kp == PSF_SPLIT_BF16 && a.K < kSmallK) kp = PSF_FP32;
+  if (kp == PSF_SPLIT_BF16 && K < kSmallK) kp = PSF_FP32;
   // the mixed and stochastic forms need many bins, and exist for the
-  // symmetric form only (every source of a launch shares the form)
-  if ((kp == PSF_MIXED_FP16 || kp == PSF_SR_FP16) && (a.K < kMixedMinK || !a.src[0].sym)) kp = PSF_SPLIT_FP16;
+  // symmetric form only
+  if ((kp == PSF_MIXED_FP16 || kp == PSF_SR_FP16) && (K < kMixedMinK || !sym)) kp = PSF_SPLIT_FP16;
   return kp;
 }
+
+// (every source of a launch shares the form)
+int contraction_prec(int prec, const BatchArgs& a) { return launch_prec(prec, a.K, a.src[0].sym != 0); }
 
 int run_batch(int prec, const BatchArgs& a, int64_t n_wg, hipStream_t s) {
   hipEvent_t ev0;

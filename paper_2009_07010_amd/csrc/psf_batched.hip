@@ -93,26 +93,30 @@ int parse_tuning(const char* json, std::vector<Tuning>* out) {
   return PSF_OK;
 }
 
-// Work items per CU when the caller gives no table: one for the 257- and
-// 129-pixel families, whose items are large; four for the 65-pixel family,
-// whose kernel runs two workgroups per CU (two items each); two otherwise.
-int default_items_per_cu(const Family& f) {
-  if (f.tbi0 == 9 && (f.tbi1 == 8 || f.tbi1 == 9)) return 1;
+// Work items per CU when the caller gives no table (kp: the precision the
+// contraction runs in): one for the 257- and 129-pixel families, whose
+// items are large, in the forms that run one workgroup per CU; four for the
+// 65-pixel family, whose kernel runs two workgroups per CU (two items each);
+// in the stochastic form, which runs two workgroups per CU for every
+// family, two for the 257-pixel family and four for the 129-pixel one; two
+// otherwise.
+int default_items_per_cu(const Family& f, int kp) {
+  if (f.tbi0 == 9 && (f.tbi1 == 8 || f.tbi1 == 9)) return kp != PSF_SR_FP16 ? 1 : f.tbi1 == 8 ? 2 : 4;
   if (f.tbi0 == 5 && f.tbi1 == 5 && f.tbj0 == 5) return 4;
   return kDefaultItemsPerCU;
 }
 
 // Persistent contraction workgroups for a launch of `items` work items of
-// this family: one per CU, two where the kernel runs two per CU.
-int64_t launch_wgs(const TilePlan& t, int64_t items) {
-  return std::min<int64_t>(items, static_cast<int64_t>(kComputeUnits) * tile_wgs_per_cu(t));
+// this family in precision kp: one per CU, two where the kernel runs two.
+int64_t launch_wgs(const TilePlan& t, int64_t items, int kp) {
+  return std::min<int64_t>(items, static_cast<int64_t>(kComputeUnits) * tile_wgs_per_cu(t, kp));
 }
 constexpr int kMaxDefaultItemsPerCU = 4;
 
-Tuning tuning_for(const std::vector<Tuning>& table, const Family& f) {
+Tuning tuning_for(const std::vector<Tuning>& table, const Family& f, int kp) {
   for (const Tuning& t : table)
     if (t.fam == f) return t;
-  return {f, default_items_per_cu(f), kFlushChunks};
+  return {f, default_items_per_cu(f, kp), kFlushChunks};
 }
 
 // Group boundaries: sources ordered by family (stable), then cut into groups
@@ -197,7 +201,7 @@ int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* 
   float* partial = reinterpret_cast<float*>(base + align_up(rec_area, 256));
   const ObsView ov = view(obs);
   for (const Group& g : groups) {
-    const Tuning tu = tuning_for(table, g.fam);
+    const Tuning tu = tuning_for(table, g.fam, launch_prec(prec, obs->K, g.fam.sym != 0));
     const GroupPlan gp = plan_group(obs, h, g, prec, tu.items_per_cu);
     BatchArgs a;
     a.n_src = static_cast<int>(g.idx.size());
@@ -227,7 +231,7 @@ int run_batched(const psf_obs* obs, int n_src, const psf_src* h, const psf_src* 
       item0 += tile_plan_items(gp.plans[q].tp);
       poff += align_up(gp.plans[q].partial_elems, 64);
     }
-    const int64_t n_wg = launch_wgs(gp.plans[0].tp, gp.items);
+    const int64_t n_wg = launch_wgs(gp.plans[0].tp, gp.items, contraction_prec(prec, a));
     int rc = run_batch(prec, a, n_wg, st);
     if (rc != PSF_OK) return rc;
   }
@@ -352,7 +356,7 @@ int psf_autotune(const psf_obs* obs, int32_t n_src, const psf_src* h_srcs, int p
         a.K = obs->K;
         a.src[0] = src_plan(&src, plan, rec, c, partial, P, nullptr);
         a.n_items = tile_plan_items(plan.tp);
-        const int64_t n_wg = launch_wgs(plan.tp, a.n_items);
+        const int64_t n_wg = launch_wgs(plan.tp, a.n_items, contraction_prec(prec, a));
         constexpr int kReps = 3;
         const int kp = contraction_prec(prec, a);
         if ((e = launch_patch(kp, a, n_wg, s)) != hipSuccess) {  // warm-up

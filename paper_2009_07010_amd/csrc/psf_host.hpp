@@ -57,8 +57,10 @@ PatchPlan plan_patch_items(const psf_obs* o, const psf_src* s, int prec, double 
 // Tile plan with about target_wgs work items.
 PatchPlan plan_patch(const psf_obs* o, const psf_src* s, int prec, int target_wgs);
 size_t patch_workspace(const psf_obs* o, const PatchPlan& p);
-// The precision a contraction launch of `a` runs in for the caller's prec
-// (small K and non-symmetric patches change it, see kSmallK, kMixedMinK).
+// The precision a contraction runs in for the caller's prec, K bins and
+// form (small K and non-symmetric patches change it, see kSmallK,
+// kMixedMinK); contraction_prec for the sources of a launch.
+int launch_prec(int prec, int64_t K, bool sym);
 int contraction_prec(int prec, const BatchArgs& a);
 
 // The contraction and finalise of one patch from per-bin records (u', v')

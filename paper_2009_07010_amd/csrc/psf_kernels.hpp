@@ -124,8 +124,9 @@ void plan_tiles(int nbi, int nbj, TilePlan* tp);
 // 65, 129 or 257 and nm falls in the same tile family).
 bool sym_patch_size(int nl, int nm);
 // Contraction workgroups one compute unit runs at once for this tile plan
-// (its kernel's occupancy): 2 for the 5 x 5 block tiles, else 1.
-int tile_wgs_per_cu(const TilePlan& t);
+// and launch precision (its kernel's occupancy): 2 for the 5 x 5 block tiles
+// and for the stochastic form, else 1.
+int tile_wgs_per_cu(const TilePlan& t, int prec);
 // Blocks of the busiest SIMD (its two contraction waves) of a tbi x tbj tile.
 int tile_max_simd_blocks(int tbi, int tbj, bool sym);
 size_t tile_plan_partial_elems(const TilePlan& tp);
