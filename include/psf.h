@@ -106,7 +106,7 @@ typedef enum {
  * per term instead of one): measured 7e-8 to 6.3e-6 of the peak on the
  * tests' workloads (the largest on the precision workload's 2.96 deg
  * source, against a normaliser that is a lower bound of the patch's peak),
- * 6.7e-7 over every pixel of the uniform-bin 257 x 257 PSF.  Same
+ * 6.7e-7 to 8.4e-7 over every pixel of the uniform-bin 257 x 257 PSF.  Same
  * conditions and fallbacks as PSF_MIXED_FP16. */
 
 /* Flag OR-ed into prec for psf_patch, psf_patch_batched and
