@@ -146,3 +146,43 @@ def test_backward_takes_split_fp16(pk, medium, prec):
     b = pk.patch_backward(dobs, srcs, G, "split_fp16")
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", FORMS)
+def test_graph_capture_and_replay_with_new_directions(pk, medium, refs, prec):
+    """A batched call of the three symmetric families captured into a graph
+    (after an eager call, which gives each kernel its registers' scratch):
+    replays equal the eager result bit for bit, with unrelated eager work in
+    between, and a replay after new directions are written to the device
+    source array equals an eager call at those directions."""
+    obs, dobs = medium
+    srcs = [refs[0][0], refs[1][0], refs[3][0]]
+    h, d = pk.device_sources(srcs)
+    ws = pk.Workspace()
+    total = sum(s.nl * s.nm for s in srcs)
+    eager = pk.patch_batched(dobs, srcs, prec=prec, workspace=ws, d_srcs=d).clone()
+    out = torch.zeros(total, dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        pk.patch_batched(dobs, srcs, prec=prec, workspace=ws, d_srcs=d, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pk.patch_batched(dobs, srcs, prec=prec, workspace=ws, d_srcs=d, out=out)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda")
+        junk.sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+    moved = [s.with_direction(s.l0 + 2e-6, s.m0 - 3e-6) for s in srcs]
+    pk.set_directions(d, torch.tensor([[s.l0, s.m0] for s in moved], dtype=torch.float64, device="cuda"))
+    g.replay()
+    torch.cuda.synchronize()
+    eager2 = pk.patch_batched(dobs, moved, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out, eager2)
+    assert not torch.equal(eager2, eager)
