@@ -125,7 +125,7 @@ def test_backward_config3_first_64_baselines(pk, prec):
     _check(g_lm, g_f, ref[:, :2], ref[:, 2], f"config3/64bl {prec}", flux_scale=meta["flux_scale"])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "sr_fp16"])
 def test_backward_config3_full(pk, prec):
     tag = "config3_seed0"
     if not os.path.exists(os.path.join(GOLD, tag + "_grad.npy")):

@@ -10,8 +10,9 @@ oracle at sampled pixels of the three symmetric families, on centred and
 shifted grids and for a strongly decorrelated source (peak / sum |W D| =
 0.17), <= 1e-5 of the patch's largest |P64| (bounded below by the sampled
 pixels and the value at the source); bitwise repeatability; batched against
-single calls; and its routes to split-FP16 (small K, patches without a
-symmetric form, the backward), which give split-FP16's bits.  Its accuracy
+single calls; graph capture; and the routes to split-FP16 (small K,
+patches without a symmetric form, the backward), which give split-FP16's
+bits.  Its accuracy
 on the full-size workloads is tested beside the other precisions (every
 pixel of the uniform-bin 257 x 257 PSF, the precision workload's twelve
 sources, the baseline-dependent workload's golden sources)."""
@@ -139,7 +140,7 @@ def test_routes_to_split_fp16(pk, medium, prec):
 @pytest.mark.parametrize("prec", FORMS)
 def test_backward_takes_split_fp16(pk, medium, prec):
     obs, dobs = medium
-    srcs = [_source(1.0, 2.1, 129), _source(2.5, 5.2, 65)]
+    srcs = [_source(1.0, 2.1, 129), _source(2.5, 5.2, 65), _source(0.3, 0.7, 257)]
     g = torch.Generator(device="cpu").manual_seed(5)
     G = torch.randn(sum(s.nl * s.nm for s in srcs), generator=g, dtype=torch.float32)
     a = pk.patch_backward(dobs, srcs, G, prec)
