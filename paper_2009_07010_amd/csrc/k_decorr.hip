@@ -158,11 +158,22 @@ __device__ __forceinline__ void finish_bin(const ObsView& o, int64_t k, double l
     const cf32 sa = expi_turns(up * (16.0 * dl)), sb = expi_turns(vp * (16.0 * dm));
     r.step_a = make_float2(sa.re, sa.im);
     r.step_b = make_float2(sb.re, sb.im);
-    rec_out[k] = r;
+    // records and W D are streamed out (non-temporal stores: they exceed
+    // every cache at the sizes that matter, 10.6 GB per source at K = 265M;
+    // 5.35 against 5.58 ms per source there)
+    static_assert(sizeof(BinRec) == 32 && offsetof(BinRec, vp) == 8 && offsetof(BinRec, step_a) == 16 &&
+                      offsetof(BinRec, step_b) == 24,
+                  "the record is stored as four 8-byte words");
+    double* q = reinterpret_cast<double*>(rec_out + k);
+    __builtin_nontemporal_store(r.up, q);
+    __builtin_nontemporal_store(r.vp, q + 1);
+    __builtin_nontemporal_store(__builtin_bit_cast(double, r.step_a), q + 2);
+    __builtin_nontemporal_store(__builtin_bit_cast(double, r.step_b), q + 3);
   }
   const float W = o.W[k];
   const float cre = W * dre, cim = W * dim;
-  if (c_out != nullptr) c_out[k] = make_float2(cre, cim);
+  if (c_out != nullptr)
+    __builtin_nontemporal_store(__builtin_bit_cast(double, make_float2(cre, cim)), reinterpret_cast<double*>(c_out + k));
   if (kGrad && coef_out != nullptr && has_grad) {
     // 2 pi i c t = 2 pi t (-Im c, Re c) for real t.  All five vectors are
     // scaled by kAdjointScale (a power of two, exact) so that they stay in
