@@ -451,8 +451,14 @@ __device__ __forceinline__ void store_pair(lds_t* hi_plane, int lo_off, int gstr
 __device__ __forceinline__ void store_pair_sr(lds_t* plane, int row, int gv, float v0, float v1, uint32_t r0,
                                               uint32_t r1) {
   typedef __attribute__((address_space(3))) uint32_t lds_u32;
-  f16x2_t h = {};
+  // each conversion writes one half and keeps the other; the two together
+  // write both, so the initial value is never read (left undefined, so that
+  // no register is cleared for it)
+  f16x2_t h;
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wuninitialized"
   h = __builtin_amdgcn_cvt_sr_f16_f32(h, v0, r0, false);
+#pragma clang diagnostic pop
   h = __builtin_amdgcn_cvt_sr_f16_f32(h, v1, r1, true);
   *reinterpret_cast<lds_u32*>(plane + row * kRowBytes + swz(row, gv >> 2) + (gv & 3) * 4) =
       __builtin_bit_cast(uint32_t, h);
@@ -469,7 +475,8 @@ __device__ __forceinline__ void store_pair_sr(lds_t* plane, int row, int gv, flo
 // record; along the units the split forms use the real three-term
 // recurrence (one fused multiply-add per written value; both parts when
 // both are written), the FP32 form the complex product.  Past the end of
-// the slice the last bin is read and its coefficient (carried by B) is 0.
+// the slice the records and coefficients read as 0 (see fetch), so the
+// coefficient (carried by B) is 0.
 template <int PREC, int TBI, int TBJ, bool IS_A>
 struct GenSym {
   using G = TileGeom<PREC, TBI, TBJ, true>;
@@ -500,9 +507,11 @@ struct GenSym {
   double ru[P][2];  // B: u' (for the offset factor)
   cf32 rst[P][2];
   cf32 rcc[P][2];
-  bool rok[P][2];
+  bool rok[P][2];      // pointer form: the bin lies inside the slice
   uint32_t rrw[P][2];  // stochastic rounding: the bins' random words
   uint32_t rw[2];
+  uint32_t wl;  // A, stochastic rounding: this thread's part of the rows' word
+  int vo, vc;   // byte offsets of this thread's first bin in a chunk's records and coefficients
   cf32 z[2], zp[2];
   float tc[2];
   lds_t* plane;
@@ -518,37 +527,88 @@ struct GenSym {
     cptr = a.c;
     kb = kb_;
     ke = ke_;
+    // kept opaque, so that the compiler adds the per-bin and per-field
+    // constants as the load instructions' immediate offsets instead of
+    // keeping one offset register per load
+    if (BUF) {
+      vo = 2 * gv * static_cast<int>(sizeof(BinRec));
+      vc = 2 * gv * static_cast<int>(sizeof(float2));
+      asm volatile("" : "+v"(vo));
+      asm volatile("" : "+v"(vc));
+    }
+    if (BUF && SR && IS_A) {
+      wl = static_cast<uint32_t>(2 * gv) * kWeyl;
+      // kept opaque, so that the compiler does not fold the per-chunk sum
+      // below back into one product per bin
+      asm volatile("" : "+v"(wl));
+    }
   }
+  static constexpr uint32_t kWeyl = 0x9E3779B1u;
+  // How a chunk's records and coefficients are read (same values either
+  // way).  Buffer form: through buffer resources that start at the chunk's
+  // first bin and end at the slice's end (ke), so bins past it read as 0
+  // (u' = v' = 0, a zero step and c = 0: their B values are 0, no
+  // contribution, and their A values finite); the resources are uniform
+  // (scalar) and a thread's offsets into them fixed, so no per-bin address
+  // arithmetic remains (65- and 129-pixel stochastic families 4-6% faster).
+  // Pointer form, kept for the 257-pixel stochastic tiles: those sit at the
+  // 128-register limit of four waves per SIMD, where the buffer form's
+  // resource registers made the allocator spill inside the chunk loop (9%
+  // slower); past the slice's end it reads the last bin and takes c = 0.
+  static constexpr bool BUF = !(PREC == kSRFP16 && TBJ >= 17);
+  // The random word of bin kg: for the rows kg times the golden ratio mod
+  // 2^32, whose top bits (the ones the conversion uses) are equidistributed
+  // in kg; for the columns a 32-bit mixing hash of kg (multiply-xorshift
+  // finaliser), independent of the rows' word.
+  static __device__ __forceinline__ uint32_t col_word(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+  }
+  // Bin kg = k0 + 2 gv + e of chunk n (k0 = kb + 32 n).
   __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok,
                                         uint32_t& rwd) const {
-    const int64_t kg = kb + n * kPatchChunkSym + 2 * gv + e;
-    // the random word of bin kg: for the rows kg times the golden ratio
-    // mod 2^32, whose top bits (the ones the conversion uses) are
-    // equidistributed in kg; for the columns a 32-bit mixing hash of kg
-    // (multiply-xorshift finaliser), independent of the rows' word
-    if (SR) {
-      if (IS_A) {
-        rwd = static_cast<uint32_t>(kg) * 0x9E3779B1u;
-      } else {
-        uint32_t h = static_cast<uint32_t>(kg);
-        h ^= h >> 16;
-        h *= 0x85EBCA6Bu;
-        h ^= h >> 13;
-        h *= 0xC2B2AE35u;
-        h ^= h >> 16;
-        rwd = h;
+    const int64_t k0 = kb + n * kPatchChunkSym;
+    const int j = 2 * gv + e;
+    if constexpr (!BUF) {
+      const int64_t kg = k0 + j;
+      if (SR) rwd = IS_A ? static_cast<uint32_t>(kg) * kWeyl : col_word(static_cast<uint32_t>(kg));
+      ok = kg < ke;
+      const int64_t kc = ok ? kg : ke - 1;
+      const BinRec* r = recs + kc;
+      f = IS_A ? r->up : r->vp;
+      const float2 s = IS_A ? r->step_a : r->step_b;
+      st = {s.x, s.y};
+      if (!IS_A) {
+        u = r->up;
+        const float2 c = cptr[kc];
+        cc = {c.x, c.y};
       }
+      return;
     }
-    ok = kg < ke;
-    const int64_t kc = ok ? kg : ke - 1;
-    const BinRec* r = recs + kc;
-    f = IS_A ? r->up : r->vp;
-    const float2 s = IS_A ? r->step_a : r->step_b;
-    st = {s.x, s.y};
-    if (!IS_A) {
-      u = r->up;
-      const float2 c = cptr[kc];
-      cc = {c.x, c.y};
+    // the rows' word as (k0 + e) times the multiplier (uniform) plus this
+    // thread's part
+    if (SR) rwd = IS_A ? static_cast<uint32_t>(k0 + e) * kWeyl + wl : col_word(static_cast<uint32_t>(k0 + j));
+    const int64_t left = ke - k0;
+    const int nb = left <= 0 ? 0 : left >= kPatchChunkSym ? kPatchChunkSym : static_cast<int>(left);
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<BinRec*>(recs + k0), 0, nb * static_cast<int>(sizeof(BinRec)), 0x00020000);
+    const int ro = vo + e * static_cast<int>(sizeof(BinRec));
+    if (IS_A) {
+      f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rr, ro + offsetof(BinRec, up), 0, 0));
+      st = __builtin_bit_cast(cf32, __builtin_amdgcn_raw_buffer_load_b64(rr, ro + offsetof(BinRec, step_a), 0, 0));
+    } else {
+      const u32x4_t uv = __builtin_amdgcn_raw_buffer_load_b128(rr, ro + offsetof(BinRec, up), 0, 0);
+      u = __builtin_bit_cast(double, __builtin_shufflevector(uv, uv, 0, 1));
+      f = __builtin_bit_cast(double, __builtin_shufflevector(uv, uv, 2, 3));
+      st = __builtin_bit_cast(cf32, __builtin_amdgcn_raw_buffer_load_b64(rr, ro + offsetof(BinRec, step_b), 0, 0));
+      const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float2*>(cptr + k0), 0, nb * static_cast<int>(sizeof(float2)), 0x00020000);
+      cc = __builtin_bit_cast(cf32,
+                              __builtin_amdgcn_raw_buffer_load_b64(rcs, vc + e * static_cast<int>(sizeof(float2)), 0, 0));
     }
   }
   __device__ __forceinline__ void prime() {
@@ -564,7 +624,7 @@ struct GenSym {
       z[e] = expi_turns_hw(rf[0][e] * pos0);
       const cf32 zs = rst[0][e];
       if (!IS_A) {
-        cf32 cc = rok[0][e] ? rcc[0][e] : cf32{0.f, 0.f};
+        cf32 cc = BUF || rok[0][e] ? rcc[0][e] : cf32{0.f, 0.f};
         // a grid not centred on the source: the row-independent factor
         // exp(2 pi i u' delta) joins the coefficient (FP64-reduced, used once)
         if (delta != 0.0) cc = cmul(cc, expi_turns_hw(ru[0][e] * delta));
