@@ -527,15 +527,9 @@ struct GenSym {
     cptr = a.c;
     kb = kb_;
     ke = ke_;
-    // kept opaque, so that the compiler adds the per-bin and per-field
-    // constants as the load instructions' immediate offsets instead of
-    // keeping one offset register per load
-    if (BUF) {
-      vo = 2 * gv * static_cast<int>(sizeof(BinRec));
-      vc = 2 * gv * static_cast<int>(sizeof(float2));
-      asm volatile("" : "+v"(vo));
-      asm volatile("" : "+v"(vc));
-    }
+    vo = 2 * gv * static_cast<int>(sizeof(BinRec));
+    vc = 2 * gv * static_cast<int>(sizeof(float2));
+    if (BUF && PREC != kSRFP16) asm volatile("" : "+v"(vo), "+v"(vc));
     if (BUF && SR && IS_A) {
       wl = static_cast<uint32_t>(2 * gv) * kWeyl;
       // kept opaque, so that the compiler does not fold the per-chunk sum
@@ -550,12 +544,13 @@ struct GenSym {
   // (u' = v' = 0, a zero step and c = 0: their B values are 0, no
   // contribution, and their A values finite); the resources are uniform
   // (scalar) and a thread's offsets into them fixed, so no per-bin address
-  // arithmetic remains (65- and 129-pixel stochastic families 4-6% faster).
-  // Pointer form, kept for the 257-pixel stochastic tiles: those sit at the
-  // 128-register limit of four waves per SIMD, where the buffer form's
-  // resource registers made the allocator spill inside the chunk loop (9%
-  // slower); past the slice's end it reads the last bin and takes c = 0.
-  static constexpr bool BUF = !(PREC == kSRFP16 && TBJ >= 17);
+  // arithmetic remains (65- and 129-pixel stochastic families 4-7% faster).
+  // Pointer form, kept for the B waves of the 257-pixel stochastic tiles:
+  // that kernel sits at the 128-register limit of four waves per SIMD,
+  // where the buffer form on both sides made the allocator spill inside the
+  // chunk loop (9% slower); past the slice's end it reads the last bin and
+  // takes c = 0.
+  static constexpr bool BUF = !(PREC == kSRFP16 && TBJ >= 17 && !IS_A);
   // The random word of bin kg: for the rows kg times the golden ratio mod
   // 2^32, whose top bits (the ones the conversion uses) are equidistributed
   // in kg; for the columns a 32-bit mixing hash of kg (multiply-xorshift
@@ -569,8 +564,21 @@ struct GenSym {
     return h;
   }
   // Bin kg = k0 + 2 gv + e of chunk n (k0 = kb + 32 n).
-  __device__ __forceinline__ void fetch(int64_t n, int e, double& f, double& u, cf32& st, cf32& cc, bool& ok,
-                                        uint32_t& rwd) const {
+  // The thread's offsets for one chunk, kept opaque to the compiler so that
+  // the per-bin and per-field constants added to them become the load
+  // instructions' immediate offsets rather than one register per load: in
+  // the stochastic form a fresh copy per chunk, which the compiler cannot
+  // hoist out of the chunk loop either (its four waves per SIMD leave no
+  // registers for hoisted offsets: 1-2% faster), elsewhere the offsets made
+  // opaque once (a copy per chunk was 2% slower for the two-wave 257-pixel
+  // split kernel).
+  __device__ __forceinline__ int2 offsets() const {
+    int2 v = {vo, vc};
+    if (BUF && PREC == kSRFP16) asm volatile("" : "+v"(v.x), "+v"(v.y));
+    return v;
+  }
+  __device__ __forceinline__ void fetch(int64_t n, int e, int2 vof, double& f, double& u, cf32& st, cf32& cc,
+                                        bool& ok, uint32_t& rwd) const {
     const int64_t k0 = kb + n * kPatchChunkSym;
     const int j = 2 * gv + e;
     if constexpr (!BUF) {
@@ -596,7 +604,7 @@ struct GenSym {
     const int nb = left <= 0 ? 0 : left >= kPatchChunkSym ? kPatchChunkSym : static_cast<int>(left);
     const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<BinRec*>(recs + k0), 0, nb * static_cast<int>(sizeof(BinRec)), 0x00020000);
-    const int ro = vo + e * static_cast<int>(sizeof(BinRec));
+    const int ro = vof.x + e * static_cast<int>(sizeof(BinRec));
     if (IS_A) {
       f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rr, ro + offsetof(BinRec, up), 0, 0));
       st = __builtin_bit_cast(cf32, __builtin_amdgcn_raw_buffer_load_b64(rr, ro + offsetof(BinRec, step_a), 0, 0));
@@ -608,14 +616,16 @@ struct GenSym {
       const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<float2*>(cptr + k0), 0, nb * static_cast<int>(sizeof(float2)), 0x00020000);
       cc = __builtin_bit_cast(cf32,
-                              __builtin_amdgcn_raw_buffer_load_b64(rcs, vc + e * static_cast<int>(sizeof(float2)), 0, 0));
+                              __builtin_amdgcn_raw_buffer_load_b64(rcs, vof.y + e * static_cast<int>(sizeof(float2)), 0, 0));
     }
   }
   __device__ __forceinline__ void prime() {
 #pragma unroll
-    for (int j = 0; j < P; ++j)
+    for (int j = 0; j < P; ++j) {
+      const int2 vof = offsets();
 #pragma unroll
-      for (int e = 0; e < 2; ++e) fetch(j, e, rf[j][e], ru[j][e], rst[j][e], rcc[j][e], rok[j][e], rrw[j][e]);
+      for (int e = 0; e < 2; ++e) fetch(j, e, vof, rf[j][e], ru[j][e], rst[j][e], rcc[j][e], rok[j][e], rrw[j][e]);
+    }
   }
   __device__ __forceinline__ void begin(lds_t* smem, int buf) {
 #pragma unroll
@@ -702,9 +712,10 @@ struct GenSym {
         rok[j][e] = rok[j + 1][e];
         rrw[j][e] = rrw[j + 1][e];
       }
+    const int2 vof = offsets();
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      fetch(n, e, rf[P - 1][e], ru[P - 1][e], rst[P - 1][e], rcc[P - 1][e], rok[P - 1][e], rrw[P - 1][e]);
+      fetch(n, e, vof, rf[P - 1][e], ru[P - 1][e], rst[P - 1][e], rcc[P - 1][e], rok[P - 1][e], rrw[P - 1][e]);
   }
 };
 
